@@ -1,0 +1,200 @@
+"""Benchmark: effective TFLOP/s (2mnk/t) of Strassen-fused GEMM at one and two
+levels against the plain MFMA GEMM of the same kernels (levels = 0), fp32,
+m = n = k = 16384, on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--levels L]
+
+A step is one strassen_gemm call (C := A*B + C) on device-resident seeded
+inputs (A, B, C ~ U[-1, 1]).  Every level 0, 1, 2 is timed: W untimed calls,
+then K calls between two synchronisations and device events.  `value` is the
+effective rate of the headline level (--levels, default 1); all three levels
+are reported under "levels".  The roofline object describes the dominant
+kernel of the headline level, timed per launch with HIP events recorded by
+the library itself on the launch stream.  The CPU oracle is timed on a
+bounded sample of rows of the same product (cpu_baseline).
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP32_MFMA_PEAK = 157.3  # TFLOP/s, MI355X dense fp32 matrix peak
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--levels", type=int, default=1, choices=[0, 1, 2])
+    p.add_argument("--size", type=int, default=16384)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    return p.parse_args()
+
+
+def cpu_baseline(A, B, C, target_s):
+    """The oracle's classical fp64 GEMM on the first R rows of the product,
+    R sized for about target_s seconds; rate scaled to TFLOP/s."""
+    import numpy as np
+    import oracle
+
+    n, k = B.shape[1], A.shape[1]
+    Bd = oracle._f64(B)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+
+    def run(rows):
+        Ad = oracle._f64(A[:rows])
+        Cd = oracle._f64(C[:rows])
+        t0 = time.perf_counter()
+        oracle._load().oracle_gemm_f64(rows, n, k, oracle._ptr(Ad), k, oracle._ptr(Bd), n,
+                                       oracle._ptr(Cd), n, 1.0, 1.0)
+        return time.perf_counter() - t0
+
+    probe = max(threads, 4)
+    t = run(probe)
+    rows = int(min(A.shape[0], max(probe, probe * target_s / max(t, 1e-6))))
+    rows = max(threads, (rows // threads) * threads)
+    t = run(rows)
+    flops = 2.0 * rows * n * k
+    del np
+    return {"value": flops / t / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": "classical fp64 oracle_gemm_f64 on the first %d of %d rows of C = A*B + C "
+                      "(n = k = %d), %.1f s" % (rows, A.shape[0], n, t)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (this build has no multi-GPU path); "
+              "got --gpus %d" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1808_07984_amd as sg
+    from paper_1808_07984_amd import inputs
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    N = args.size
+    m = n = k = N
+    log("generating inputs %dx%d fp32" % (N, N))
+    A_h = inputs.uniform(m, k, inputs.SEED_A)
+    B_h = inputs.uniform(k, n, inputs.SEED_B)
+    C_h = inputs.uniform(m, n, inputs.SEED_C)
+    A, B, C0 = A_h.to(dev), B_h.to(dev), C_h.to(dev)
+    C = C0.clone()
+    stream = torch.cuda.current_stream(dev)
+
+    # Sampled correctness check of each level on the benchmark inputs.
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(0)
+    rows, cols = rng.integers(0, m, 256), rng.integers(0, n, 256)
+    want = oracle.gemm_entries(A_h, B_h, C_h, rows, cols, 1.0, 1.0)
+    scale = k * float(A_h.abs().max()) * float(B_h.abs().max()) + float(C_h.abs().max())
+    parity = {}
+    for L in (0, 1, 2):
+        C.copy_(C0)
+        sg.gemm(A, B, C, 1.0, 1.0, levels=L)
+        torch.cuda.synchronize()
+        got = C[torch.as_tensor(rows, device=dev), torch.as_tensor(cols, device=dev)].double().cpu().numpy()
+        en = float(np.abs(got - want).max()) / (2.0 ** -23 * scale)
+        parity["L%d" % L] = round(en, 4)
+        log("parity L%d sampled e_norm %.4f (tolerance %g)" % (L, en, 2.0 ** (L + 1)))
+        if not en <= 2.0 ** (L + 1):
+            raise SystemExit("parity failure at levels=%d" % L)
+
+    per_level = {}
+    headline_records = None
+    for L in (0, 1, 2):
+        info = sg.plan_info(m, n, k, L)
+        for _ in range(args.warmup):
+            sg.gemm(A, B, C, 1.0, 1.0, levels=L)
+        torch.cuda.synchronize()
+        if L == args.levels:
+            sg.strassen_profile_start()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            sg.gemm(A, B, C, 1.0, 1.0, levels=L)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1) / args.steps
+        if L == args.levels:
+            rc, headline_records = sg.strassen_profile_stop(capacity=1 << 14)
+            if rc < 0:
+                raise SystemExit("strassen_profile_stop failed: %d" % rc)
+        eff = 2.0 * m * n * k / (ms * 1e-3) / 1e12
+        exe = info.executed_flops / (ms * 1e-3) / 1e12
+        per_level["L%d" % L] = {"ms_per_step": round(ms, 4), "effective_tflops": round(eff, 2),
+                                "executed_tflops": round(exe, 2),
+                                "mfma_frac_executed": round(exe / FP32_MFMA_PEAK, 4),
+                                "launches_per_step": info.n_launches}
+        log("L%d: %.3f ms/step  effective %.1f TFLOP/s  executed %.1f TFLOP/s  (wall %.2f s)"
+            % (L, ms, eff, exe, wall))
+
+    # Dominant kernel of the headline level: the instantiation with the most
+    # device time; achieved = its executed flops / its launch time.
+    by_kernel = {}
+    for r in headline_records:
+        name = r.kernel.decode()
+        t = by_kernel.setdefault(name, [0.0, 0.0, 0])
+        t[0] += r.ms
+        t[1] += r.flops
+        t[2] += 1
+    dom = max(by_kernel.items(), key=lambda kv: kv[1][0])
+    dom_name, (dom_ms, dom_flops, dom_n) = dom
+    achieved = dom_flops / (dom_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP32_MFMA_PEAK,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_MFMA_PEAK, 4), "traffic": None,
+                "kernel": dom_name, "launches": dom_n,
+                "avg_launch_ms": round(dom_ms / dom_n, 4),
+                "flops_per_launch": dom_flops / dom_n}
+
+    head = per_level["L%d" % args.levels]
+    result = {
+        "metric": "effective TFLOP/s (2mnk/t) Strassen 1L/2L vs plain GEMM, m=n=k=16384",
+        "value": head["effective_tflops"],
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "fp32 C = A*B + C, m=n=k=%d, row-major, A,B,C ~ U[-1,1] seeded, "
+                               "%d-level Strassen (levels 0/1/2 all timed)" % (N, args.levels),
+                   "m": m, "n": n, "k": k, "levels": args.levels, "alpha": 1.0, "beta": 1.0},
+        "levels": per_level,
+        "parity_sampled_e_norm": parity,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        result["cpu_baseline"] = cpu_baseline(A_h, B_h, C_h, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,172 @@
+/*
+ * strassen.h -- C ABI of the Strassen-fused GEMM library for AMD MI355X (gfx950).
+ *
+ * Computes C := alpha * A * B + beta * C (Introduction, eq. "prime") with
+ * zero, one or two levels of Strassen's seven-product scheme (Method section,
+ * eq. "gpu_allops"; two levels as in the "Two-Level Strassen's Algorithm"
+ * section).  Every product of the scheme is one instance of the general
+ * primitive M = (sum of signed A blocks)(sum of signed B blocks); C_o += g_o M
+ * (eq. "straprim1"): the operand sums are formed while tiles are staged into
+ * LDS and the product is scattered with its signs into up to four C blocks in
+ * the kernel epilogue (Strassen's Algorithm on NVIDIA GPUs section), so the
+ * library needs no workspace and allocates no device memory.
+ *
+ * Layout: all matrices are row-major.  Element (i, j) of an r x c matrix X
+ * with leading dimension ldX is X[i * ldX + j]; ldX >= max(1, c).
+ *   A is m x k (lda), B is k x n (ldb), C is m x n (ldc).
+ * A and B are read-only device pointers; C is an in/out device pointer.  The
+ * caller owns every buffer.  A or B may not overlap C.
+ *
+ * Sizes that 2^levels does not divide are handled by virtual zero padding
+ * inside the tiles ("Handling the Fringes" section): blocks that extend past
+ * the matrix read zeros and write nothing.  Nothing outside the logical
+ * matrices (the ld padding) is read or written.
+ *
+ * Asynchrony: calls enqueue kernels on a HIP stream and return; execution
+ * errors surface at the caller's next synchronisation.  Results are
+ * deterministic: the seven (or 49) products are launched in batches whose C
+ * write sets are disjoint (Task Parallelism section, batching by variant), so
+ * no atomics are used.
+ *
+ * Error convention (returned int):
+ *    0              success
+ *   -i              the i-th argument of the called function is invalid
+ *                   (1-based, in that function's parameter order)
+ *   > 0             a hipError_t reported by the HIP runtime (no device,
+ *                   launch failure, ...)
+ * strassen_error_string() describes a code.  No C++ exception crosses the ABI.
+ *
+ * Degenerate cases (BLAS conventions; the paper fixes alpha = beta = 1):
+ *   m == 0 or n == 0      nothing is done (returns 0).
+ *   k == 0 or alpha == 0  C := beta * C; A and B are not read.
+ *   beta == 0             C is write-only; NaN/Inf already in C do not
+ *                         propagate.
+ */
+#ifndef STRASSEN_H
+#define STRASSEN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Storage type of A and B.  C is always fp32 and products accumulate in
+ * fp32 on the matrix cores.  For the 16-bit types the signed operand sums
+ * are formed in fp32 from the stored values and rounded once (to nearest,
+ * ties to even) to the operand type before the MFMA. */
+typedef enum {
+    STRASSEN_F32 = 0,
+    STRASSEN_BF16 = 1,
+    STRASSEN_F16 = 2
+} strassen_dtype_t;
+
+/* Arithmetic mode.
+ *   PLAIN   products in the storage type (fp32 MFMA for fp32 operands).
+ *   BF16X3  fp32 operands only: each fp32 operand sum x is split into
+ *           hi = bf16(x) and lo = bf16(x - hi) and the product is
+ *           hi*hi + hi*lo + lo*hi on bf16 MFMAs with fp32 accumulation. */
+typedef enum {
+    STRASSEN_MODE_PLAIN = 0,
+    STRASSEN_MODE_BF16X3 = 1
+} strassen_mode_t;
+
+#define STRASSEN_MAX_LEVELS 2
+
+/* C := alpha*A*B + beta*C, fp32 operands, `levels` in {0, 1, 2} (0 is the
+ * plain blocked GEMM with the same kernels), enqueued on the calling
+ * thread's stream (strassen_set_stream; the null stream by default).
+ * Argument indices for errors: m=1 n=2 k=3 A=4 lda=5 B=6 ldb=7 C=8 ldc=9
+ * alpha=10 beta=11 levels=12.  Overlap of A or B with C reports -8. */
+int strassen_gemm(int64_t m, int64_t n, int64_t k,
+                  const float *A, int64_t lda,
+                  const float *B, int64_t ldb,
+                  float *C, int64_t ldc,
+                  float alpha, float beta, int levels);
+
+/* Extended form.  a_type and b_type must be equal.  trans_a / trans_b = 1
+ * reads op(A) = A^T (A stored k x m, lda >= m) / op(B) = B^T (B stored
+ * n x k, ldb >= k); the product is then op(A)*op(B), m x n, and a block of
+ * op(X) is the transpose of a block of X.  hip_stream is a hipStream_t
+ * (NULL = the null stream).
+ * Argument indices: m=1 n=2 k=3 A=4 lda=5 a_type=6 trans_a=7 B=8 ldb=9
+ * b_type=10 trans_b=11 C=12 ldc=13 alpha=14 beta=15 levels=16 mode=17
+ * hip_stream=18.  Overlap of A or B with C reports -12. */
+int strassen_gemm_ex(int64_t m, int64_t n, int64_t k,
+                     const void *A, int64_t lda, strassen_dtype_t a_type, int trans_a,
+                     const void *B, int64_t ldb, strassen_dtype_t b_type, int trans_b,
+                     float *C, int64_t ldc,
+                     float alpha, float beta, int levels,
+                     strassen_mode_t mode, void *hip_stream);
+
+/* Sets the stream strassen_gemm uses on the calling thread (a hipStream_t;
+ * NULL = the null stream).  Always returns 0. */
+int strassen_set_stream(void *hip_stream);
+
+/* Description of how a call of this shape is executed. */
+typedef struct {
+    int32_t levels;            /* 0, 1 or 2 */
+    int32_t blocks_per_dim;    /* d = 2^levels */
+    int64_t sub_m, sub_n, sub_k; /* extent of one block of the d x d partition
+                                  * (ceil(dim/d), n and k rounded up to the
+                                  * vector width for levels >= 1) */
+    int32_t n_instances;       /* 7^levels products */
+    int32_t n_launches;        /* race-free batches = kernel launches */
+    int32_t tile_m, tile_n, tile_k; /* workgroup tile of the product kernel */
+    int32_t workgroups_per_instance;
+    double executed_flops;     /* 7^L * 2 * sub_m * sub_n * sub_k */
+    double classical_flops;    /* 2 * m * n * k */
+} strassen_plan_info_t;
+
+/* Fills *out for a call of this shape, dtype and mode.  Pure host
+ * computation: needs no GPU.  Argument indices: m=1 n=2 k=3 levels=4
+ * dtype=5 mode=6 out=7. */
+int strassen_plan_info(int64_t m, int64_t n, int64_t k, int levels,
+                       strassen_dtype_t dtype, strassen_mode_t mode,
+                       strassen_plan_info_t *out);
+
+/* One product of the plan.  Blocks are numbered row-major in the d x d
+ * partition: block b covers block-row b / d and block-column b % d.  Signs
+ * are +1 or -1.  c_first[o] = 1 marks the first update of C block c_block[o]
+ * in launch order: that update applies beta (C := beta*C + g*alpha*M). */
+typedef struct {
+    int32_t launch;            /* index of the kernel launch (batch) */
+    int32_t n_a, n_b, n_c;     /* W_A, W_B, W_C (Register Optimization section) */
+    int32_t a_block[4], a_sign[4];
+    int32_t b_block[4], b_sign[4];
+    int32_t c_block[4], c_sign[4], c_first[4];
+} strassen_instance_t;
+
+/* Copies the plan's products, in launch order, into out[0 .. capacity-1]
+ * and returns their number (7^levels), or a negative argument index
+ * (levels=1 out=2 capacity=3).  Pure host computation: needs no GPU. */
+int strassen_plan_instances(int levels, strassen_instance_t *out, int capacity);
+
+/* Static description of an error code; never NULL. */
+const char *strassen_error_string(int code);
+
+/* ---- measurement support (Experiment section: kernels are timed with
+ * device events) ----------------------------------------------------------
+ * While recording is on, every kernel the library launches is bracketed by
+ * two HIP events on its stream.  strassen_profile_stop() waits for those
+ * events, copies at most `capacity` records into out (oldest first), turns
+ * recording off and returns the number of records made (which may exceed
+ * capacity), or a negative argument index (out=1 capacity=2), or a positive
+ * hipError_t. */
+typedef struct {
+    char kernel[64];           /* kernel family and template variant */
+    int32_t launch;            /* launch index within its call */
+    int32_t batch;             /* products in this launch */
+    int32_t workgroups;        /* total workgroups */
+    float ms;                  /* device time between the two events */
+    double flops;              /* executed MFMA flops of this launch */
+} strassen_launch_record_t;
+
+int strassen_profile_start(void);
+int strassen_profile_stop(strassen_launch_record_t *out, int capacity);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STRASSEN_H */

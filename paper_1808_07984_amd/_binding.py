@@ -1,0 +1,147 @@
+"""ctypes binding of libstrassen.so: the C ABI of include/strassen.h with the
+same names, argument marshalling only.
+
+The library must have been built (``python -m paper_1808_07984_amd.build`` or
+``__graft_entry__.build()``); importing this module without it raises, there
+is no fallback path.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libstrassen.so")
+
+# strassen_dtype_t / strassen_mode_t
+STRASSEN_F32, STRASSEN_BF16, STRASSEN_F16 = 0, 1, 2
+STRASSEN_MODE_PLAIN, STRASSEN_MODE_BF16X3 = 0, 1
+STRASSEN_MAX_LEVELS = 2
+
+
+class strassen_plan_info_t(ctypes.Structure):
+    _fields_ = [
+        ("levels", ctypes.c_int32),
+        ("blocks_per_dim", ctypes.c_int32),
+        ("sub_m", ctypes.c_int64),
+        ("sub_n", ctypes.c_int64),
+        ("sub_k", ctypes.c_int64),
+        ("n_instances", ctypes.c_int32),
+        ("n_launches", ctypes.c_int32),
+        ("tile_m", ctypes.c_int32),
+        ("tile_n", ctypes.c_int32),
+        ("tile_k", ctypes.c_int32),
+        ("workgroups_per_instance", ctypes.c_int32),
+        ("executed_flops", ctypes.c_double),
+        ("classical_flops", ctypes.c_double),
+    ]
+
+
+class strassen_instance_t(ctypes.Structure):
+    _fields_ = [
+        ("launch", ctypes.c_int32),
+        ("n_a", ctypes.c_int32),
+        ("n_b", ctypes.c_int32),
+        ("n_c", ctypes.c_int32),
+        ("a_block", ctypes.c_int32 * 4),
+        ("a_sign", ctypes.c_int32 * 4),
+        ("b_block", ctypes.c_int32 * 4),
+        ("b_sign", ctypes.c_int32 * 4),
+        ("c_block", ctypes.c_int32 * 4),
+        ("c_sign", ctypes.c_int32 * 4),
+        ("c_first", ctypes.c_int32 * 4),
+    ]
+
+
+class strassen_launch_record_t(ctypes.Structure):
+    _fields_ = [
+        ("kernel", ctypes.c_char * 64),
+        ("launch", ctypes.c_int32),
+        ("batch", ctypes.c_int32),
+        ("workgroups", ctypes.c_int32),
+        ("ms", ctypes.c_float),
+        ("flops", ctypes.c_double),
+    ]
+
+
+# Exported functions and their signatures, in header order.
+_i64, _int, _f32, _vp = ctypes.c_int64, ctypes.c_int, ctypes.c_float, ctypes.c_void_p
+SIGNATURES = {
+    "strassen_gemm": (_int, [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _f32, _f32, _int]),
+    "strassen_gemm_ex": (_int, [_i64, _i64, _i64, _vp, _i64, _int, _int, _vp, _i64, _int, _int,
+                                _vp, _i64, _f32, _f32, _int, _int, _vp]),
+    "strassen_set_stream": (_int, [_vp]),
+    "strassen_plan_info": (_int, [_i64, _i64, _i64, _int, _int, _int,
+                                  ctypes.POINTER(strassen_plan_info_t)]),
+    "strassen_plan_instances": (_int, [_int, ctypes.POINTER(strassen_instance_t), _int]),
+    "strassen_error_string": (ctypes.c_char_p, [_int]),
+    "strassen_profile_start": (_int, []),
+    "strassen_profile_stop": (_int, [ctypes.POINTER(strassen_launch_record_t), _int]),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            "libstrassen.so is not built (%s); run `python -m paper_1808_07984_amd.build`" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+class StrassenError(RuntimeError):
+    """A non-zero return code of the C ABI."""
+
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__("%s returned %d: %s" % (where, code, strassen_error_string(code)))
+
+
+def strassen_gemm(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, levels):
+    return lib.strassen_gemm(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, levels)
+
+
+def strassen_gemm_ex(m, n, k, A, lda, a_type, trans_a, B, ldb, b_type, trans_b, C, ldc,
+                     alpha, beta, levels, mode, hip_stream):
+    return lib.strassen_gemm_ex(m, n, k, A, lda, a_type, trans_a, B, ldb, b_type, trans_b,
+                                C, ldc, alpha, beta, levels, mode, hip_stream)
+
+
+def strassen_set_stream(hip_stream):
+    return lib.strassen_set_stream(hip_stream)
+
+
+def strassen_plan_info(m, n, k, levels, dtype=STRASSEN_F32, mode=STRASSEN_MODE_PLAIN):
+    """Returns (code, strassen_plan_info_t)."""
+    out = strassen_plan_info_t()
+    rc = lib.strassen_plan_info(m, n, k, levels, dtype, mode, ctypes.byref(out))
+    return rc, out
+
+
+def strassen_plan_instances(levels, capacity=None):
+    """Returns (count_or_code, list of strassen_instance_t)."""
+    if capacity is None:
+        capacity = 7 ** max(0, min(int(levels), STRASSEN_MAX_LEVELS))
+    buf = (strassen_instance_t * max(capacity, 1))()
+    rc = lib.strassen_plan_instances(levels, buf, capacity)
+    return rc, list(buf[:max(0, min(rc, capacity))])
+
+
+def strassen_error_string(code):
+    s = lib.strassen_error_string(code)
+    return s.decode() if s else ""
+
+
+def strassen_profile_start():
+    return lib.strassen_profile_start()
+
+
+def strassen_profile_stop(capacity=4096):
+    """Returns (count_or_code, list of strassen_launch_record_t)."""
+    buf = (strassen_launch_record_t * max(capacity, 1))()
+    rc = lib.strassen_profile_stop(buf, capacity)
+    return rc, list(buf[:max(0, min(rc, capacity))])

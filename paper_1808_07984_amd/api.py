@@ -1,0 +1,62 @@
+"""torch-facing convenience layer over the C ABI.
+
+torch supplies device memory and the current stream only: ``gemm`` checks
+shapes, dtypes, devices and strides, passes raw pointers and leading
+dimensions to ``strassen_gemm_ex`` and raises on a non-zero code.  All
+arithmetic happens in the HIP kernels of libstrassen.so.
+"""
+import torch
+
+from . import _binding as B
+
+_DTYPES = {torch.float32: B.STRASSEN_F32, torch.bfloat16: B.STRASSEN_BF16,
+           torch.float16: B.STRASSEN_F16}
+_MODES = {"plain": B.STRASSEN_MODE_PLAIN, "bf16x3": B.STRASSEN_MODE_BF16X3}
+
+
+def _ld(t, name):
+    if t.dim() != 2:
+        raise ValueError("%s must be 2-D" % name)
+    if t.shape[1] > 1 and t.stride(1) != 1:
+        raise ValueError("%s must have unit stride along its second dimension" % name)
+    return max(t.stride(0), 1) if t.shape[0] > 1 else max(t.shape[1], 1)
+
+
+def gemm(A, B_, C, alpha=1.0, beta=1.0, levels=1, mode="plain", trans_a=False, trans_b=False,
+         stream=None):
+    """C := alpha * op(A) @ op(B) + beta * C in place, with `levels` levels of
+    Strassen (0 = plain blocked GEMM).  op(X) = X, or X.T when trans_x is set,
+    in which case X is passed in its stored (untransposed) layout.
+    A, B: fp32, bf16 or fp16 CUDA tensors of one dtype; C: fp32 CUDA tensor.
+    Returns C."""
+    if not (A.is_cuda and B_.is_cuda and C.is_cuda):
+        raise ValueError("A, B and C must be GPU tensors")
+    if not (A.device == B_.device == C.device):
+        raise ValueError("A, B and C must be on one device")
+    if A.dtype not in _DTYPES or B_.dtype != A.dtype:
+        raise TypeError("A and B must share a dtype among float32, bfloat16, float16")
+    if C.dtype != torch.float32:
+        raise TypeError("C must be float32")
+    if mode not in _MODES:
+        raise ValueError("mode must be one of %s" % sorted(_MODES))
+    m, k = (A.shape[1], A.shape[0]) if trans_a else (A.shape[0], A.shape[1])
+    kb, n = (B_.shape[1], B_.shape[0]) if trans_b else (B_.shape[0], B_.shape[1])
+    if kb != k or tuple(C.shape) != (m, n):
+        raise ValueError("shape mismatch: op(A) %dx%d, op(B) %dx%d, C %s" % (m, k, kb, n, tuple(C.shape)))
+    lda, ldb, ldc = _ld(A, "A"), _ld(B_, "B"), _ld(C, "C")
+    with torch.cuda.device(C.device):
+        s = stream if stream is not None else torch.cuda.current_stream(C.device)
+        rc = B.strassen_gemm_ex(m, n, k, A.data_ptr(), lda, _DTYPES[A.dtype], int(bool(trans_a)),
+                                B_.data_ptr(), ldb, _DTYPES[A.dtype], int(bool(trans_b)),
+                                C.data_ptr(), ldc, float(alpha), float(beta), int(levels),
+                                _MODES[mode], s.cuda_stream)
+    if rc != 0:
+        raise B.StrassenError(rc, "strassen_gemm_ex")
+    return C
+
+
+def plan_info(m, n, k, levels, dtype=torch.float32, mode="plain"):
+    rc, info = B.strassen_plan_info(m, n, k, levels, _DTYPES[dtype], _MODES[mode])
+    if rc != 0:
+        raise B.StrassenError(rc, "strassen_plan_info")
+    return info

@@ -1,0 +1,427 @@
+// C ABI of the library (include/strassen.h): argument validation, planning,
+// and one kernel launch per race-free batch of Strassen products.
+#include "strassen.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "kernel_args.hpp"
+#include "launch.hpp"
+#include "plan.hpp"
+
+namespace {
+
+using strassen::LaunchArgs;
+using strassen::Plan;
+using strassen::ProductArg;
+using strassen::TermArg;
+
+thread_local hipStream_t g_stream = nullptr;
+
+// ---------------------------------------------------------------------------
+// Launch recording (strassen_profile_start / strassen_profile_stop).
+// ---------------------------------------------------------------------------
+struct Record {
+    strassen_launch_record_t info;
+    hipEvent_t e0, e1;
+};
+
+struct Recorder {
+    std::mutex mu;
+    bool on = false;
+    int total = 0;
+    std::vector<Record> recs;
+    std::vector<hipEvent_t> pool;
+
+    hipError_t take(hipEvent_t *e) {
+        if (!pool.empty()) {
+            *e = pool.back();
+            pool.pop_back();
+            return hipSuccess;
+        }
+        return hipEventCreate(e);
+    }
+};
+
+Recorder &recorder() {
+    static Recorder r;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Validation.
+// ---------------------------------------------------------------------------
+constexpr int64_t kMaxDim = (int64_t)1 << 31;  // block extents are int32 in the kernels
+
+size_t elem_size(strassen_dtype_t t) { return t == STRASSEN_F32 ? 4 : 2; }
+
+bool valid_dtype(int t) { return t == STRASSEN_F32 || t == STRASSEN_BF16 || t == STRASSEN_F16; }
+
+// Bytes spanned by an r x c row-major matrix with leading dimension ld.
+uint64_t span_bytes(int64_t r, int64_t c, int64_t ld, size_t es) {
+    if (r <= 0 || c <= 0) return 0;
+    return ((uint64_t)(r - 1) * (uint64_t)ld + (uint64_t)c) * es;
+}
+
+bool overlap(const void *p, uint64_t np, const void *q, uint64_t nq) {
+    if (np == 0 || nq == 0) return false;
+    const uintptr_t a = (uintptr_t)p, b = (uintptr_t)q;
+    return a < b + nq && b < a + np;
+}
+
+struct Call {
+    int64_t m, n, k;
+    const void *A;
+    int64_t lda;
+    strassen_dtype_t a_type;
+    int trans_a;
+    const void *B;
+    int64_t ldb;
+    strassen_dtype_t b_type;
+    int trans_b;
+    float *C;
+    int64_t ldc;
+    float alpha, beta;
+    int levels;
+    strassen_mode_t mode;
+    hipStream_t stream;
+};
+
+// Returns 0 or -(index of the offending argument in strassen_gemm_ex order).
+int validate(const Call &c) {
+    if (c.m < 0 || c.m >= kMaxDim) return -1;
+    if (c.n < 0 || c.n >= kMaxDim) return -2;
+    if (c.k < 0 || c.k >= kMaxDim) return -3;
+    // A and B are read only when the product term is present.
+    const bool product = c.m > 0 && c.n > 0 && c.k > 0 && c.alpha != 0.f;
+    if (!valid_dtype(c.a_type)) return -6;
+    if (c.trans_a != 0 && c.trans_a != 1) return -7;
+    if (!valid_dtype(c.b_type) || c.b_type != c.a_type) return -10;
+    if (c.trans_b != 0 && c.trans_b != 1) return -11;
+    // stored shapes: A is m x k (k x m if transposed), B is k x n (n x k)
+    const int64_t a_rows = c.trans_a ? c.k : c.m, a_cols = c.trans_a ? c.m : c.k;
+    const int64_t b_rows = c.trans_b ? c.n : c.k, b_cols = c.trans_b ? c.k : c.n;
+    if (product && c.A == nullptr) return -4;
+    if (c.lda < (a_cols > 1 ? a_cols : 1)) return -5;
+    if (product && c.B == nullptr) return -8;
+    if (c.ldb < (b_cols > 1 ? b_cols : 1)) return -9;
+    if (c.m > 0 && c.n > 0 && c.C == nullptr) return -12;
+    if (c.ldc < (c.n > 1 ? c.n : 1)) return -13;
+    if (c.levels < 0 || c.levels > STRASSEN_MAX_LEVELS) return -16;
+    if (c.mode != STRASSEN_MODE_PLAIN && c.mode != STRASSEN_MODE_BF16X3) return -17;
+    if (c.mode == STRASSEN_MODE_BF16X3 && c.a_type != STRASSEN_F32) return -17;
+    if (product) {
+        const uint64_t nc = span_bytes(c.m, c.n, c.ldc, 4);
+        const size_t es = elem_size(c.a_type);
+        if (overlap(c.A, span_bytes(a_rows, a_cols, c.lda, es), c.C, nc)) return -12;
+        if (overlap(c.B, span_bytes(b_rows, b_cols, c.ldb, es), c.C, nc)) return -12;
+    }
+    // Not built yet: 16-bit operands, the compensated mode, transposed operands.
+    if (c.a_type != STRASSEN_F32) return -6;
+    if (c.mode != STRASSEN_MODE_PLAIN) return -17;
+    if (c.trans_a) return -7;
+    if (c.trans_b) return -11;
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Execution.
+// ---------------------------------------------------------------------------
+TermArg term(int64_t off, int64_t rows, int64_t cols, int sign, bool first) {
+    TermArg t;
+    t.off = off;
+    t.rows = (int32_t)rows;
+    t.cols = (int32_t)cols;
+    t.sign = (float)sign;
+    t.first = first ? 1 : 0;
+    return t;
+}
+
+int run(const Call &c) {
+    if (c.m == 0 || c.n == 0) return 0;
+    if (c.k == 0 || c.alpha == 0.f)
+        return (int)strassen::launch_scale(c.C, c.ldc, c.m, c.n, c.beta, c.stream);
+
+    const strassen::KernelShape ks = strassen::f32_tile_shape();
+    const Plan plan = strassen::make_plan(c.m, c.n, c.k, c.levels, ks.vec);
+    const int d = plan.d;
+
+    LaunchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.A = c.A;
+    a.B = c.B;
+    a.C = c.C;
+    a.lda = c.lda;
+    a.ldb = c.ldb;
+    a.ldc = c.ldc;
+    a.sm = (int32_t)plan.sm;
+    a.sn = (int32_t)plan.sn;
+    a.sk = (int32_t)plan.sk;
+    a.tiles_m = (int32_t)((plan.sm + ks.mt - 1) / ks.mt);
+    a.tiles_n = (int32_t)((plan.sn + ks.nt - 1) / ks.nt);
+    a.alpha = c.alpha;
+    a.beta = c.beta;
+    a.trans_a = c.trans_a;
+    a.trans_b = c.trans_b;
+
+    // 16-byte loads need aligned bases, leading dimensions and block offsets
+    // (make_plan rounds block extents along n and k to the vector width).
+    const bool vec = (c.lda % ks.vec == 0) && (c.ldb % ks.vec == 0) &&
+                     ((uintptr_t)c.A % 16 == 0) && ((uintptr_t)c.B % 16 == 0);
+
+    Recorder &rec = recorder();
+    for (size_t bi = 0; bi < plan.batches.size(); ++bi) {
+        const strassen::Batch &bt = plan.batches[bi];
+        const int batch = (int)bt.products.size();
+        for (int z = 0; z < batch; ++z) {
+            const strassen::Product &p = plan.products[bt.products[z]];
+            ProductArg &pa = a.prod[z];
+            for (int t = 0; t < p.na; ++t) {
+                const int R = p.a[t].block / d, Cc = p.a[t].block % d;
+                pa.a[t] = term(R * plan.sm * c.lda + Cc * plan.sk,
+                               strassen::block_extent(c.m, plan.sm, R),
+                               strassen::block_extent(c.k, plan.sk, Cc), p.a[t].sign, false);
+            }
+            for (int t = 0; t < p.nb; ++t) {
+                const int R = p.b[t].block / d, Cc = p.b[t].block % d;
+                pa.b[t] = term(R * plan.sk * c.ldb + Cc * plan.sn,
+                               strassen::block_extent(c.k, plan.sk, R),
+                               strassen::block_extent(c.n, plan.sn, Cc), p.b[t].sign, false);
+            }
+            for (int t = 0; t < p.nc; ++t) {
+                const int R = p.c[t].block / d, Cc = p.c[t].block % d;
+                pa.c[t] = term(R * plan.sm * c.ldc + Cc * plan.sn,
+                               strassen::block_extent(c.m, plan.sm, R),
+                               strassen::block_extent(c.n, plan.sn, Cc), p.c[t].sign,
+                               p.c_first[t]);
+            }
+        }
+
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        bool timed = false;
+        {
+            std::lock_guard<std::mutex> lk(rec.mu);
+            if (rec.on) {
+                hipError_t err = rec.take(&e0);
+                if (err == hipSuccess) err = rec.take(&e1);
+                if (err != hipSuccess) return (int)err;
+                timed = true;
+            }
+        }
+        if (timed) {
+            const hipError_t err = hipEventRecord(e0, c.stream);
+            if (err != hipSuccess) return (int)err;
+        }
+        const hipError_t err = strassen::launch_f32(bt.wa, bt.wb, bt.wc, a, batch, vec, c.stream);
+        if (err != hipSuccess) return (int)err;
+        if (timed) {
+            const hipError_t e2 = hipEventRecord(e1, c.stream);
+            if (e2 != hipSuccess) return (int)e2;
+            Record r;
+            std::memset(&r.info, 0, sizeof(r.info));
+            std::snprintf(r.info.kernel, sizeof(r.info.kernel), "%s<%d,%d,%d,%s>",
+                          strassen::f32_kernel_name(), bt.wa, bt.wb, bt.wc, vec ? "vec" : "scalar");
+            r.info.launch = (int32_t)bi;
+            r.info.batch = batch;
+            r.info.workgroups = a.tiles_m * a.tiles_n * batch;
+            r.info.flops = 2.0 * (double)batch * (double)plan.sm * (double)plan.sn * (double)plan.sk;
+            r.e0 = e0;
+            r.e1 = e1;
+            std::lock_guard<std::mutex> lk(rec.mu);
+            rec.recs.push_back(r);
+            ++rec.total;
+        }
+    }
+    return 0;
+}
+
+// Maps a strassen_gemm_ex argument index to its strassen_gemm position.
+int to_base_index(int code) {
+    switch (-code) {
+        case 1: return -1;
+        case 2: return -2;
+        case 3: return -3;
+        case 4: return -4;
+        case 5: return -5;
+        case 8: return -6;
+        case 9: return -7;
+        case 12: return -8;
+        case 13: return -9;
+        case 14: return -10;
+        case 15: return -11;
+        case 16: return -12;
+        default: return code;
+    }
+}
+
+const char *const kArgMessages[] = {
+    "invalid argument 1",  "invalid argument 2",  "invalid argument 3",  "invalid argument 4",
+    "invalid argument 5",  "invalid argument 6",  "invalid argument 7",  "invalid argument 8",
+    "invalid argument 9",  "invalid argument 10", "invalid argument 11", "invalid argument 12",
+    "invalid argument 13", "invalid argument 14", "invalid argument 15", "invalid argument 16",
+    "invalid argument 17", "invalid argument 18",
+};
+
+}  // namespace
+
+extern "C" {
+
+int strassen_gemm_ex(int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
+                     strassen_dtype_t a_type, int trans_a, const void *B, int64_t ldb,
+                     strassen_dtype_t b_type, int trans_b, float *C, int64_t ldc, float alpha,
+                     float beta, int levels, strassen_mode_t mode, void *hip_stream) {
+    const Call c{m, n, k, A, lda, a_type, trans_a, B, ldb, b_type, trans_b, C, ldc,
+                 alpha, beta, levels, mode, (hipStream_t)hip_stream};
+    const int v = validate(c);
+    if (v != 0) return v;
+    try {
+        return run(c);
+    } catch (...) {
+        return (int)hipErrorOutOfMemory;  // host allocation in the planner failed
+    }
+}
+
+int strassen_gemm(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda, const float *B,
+                  int64_t ldb, float *C, int64_t ldc, float alpha, float beta, int levels) {
+    const int r = strassen_gemm_ex(m, n, k, A, lda, STRASSEN_F32, 0, B, ldb, STRASSEN_F32, 0, C,
+                                   ldc, alpha, beta, levels, STRASSEN_MODE_PLAIN, g_stream);
+    return r < 0 ? to_base_index(r) : r;
+}
+
+int strassen_set_stream(void *hip_stream) {
+    g_stream = (hipStream_t)hip_stream;
+    return 0;
+}
+
+int strassen_plan_info(int64_t m, int64_t n, int64_t k, int levels, strassen_dtype_t dtype,
+                       strassen_mode_t mode, strassen_plan_info_t *out) {
+    if (m < 0 || m >= kMaxDim) return -1;
+    if (n < 0 || n >= kMaxDim) return -2;
+    if (k < 0 || k >= kMaxDim) return -3;
+    if (levels < 0 || levels > STRASSEN_MAX_LEVELS) return -4;
+    if (!valid_dtype(dtype)) return -5;
+    if (mode != STRASSEN_MODE_PLAIN && mode != STRASSEN_MODE_BF16X3) return -6;
+    if (mode == STRASSEN_MODE_BF16X3 && dtype != STRASSEN_F32) return -6;
+    if (out == nullptr) return -7;
+    try {
+        const strassen::KernelShape ks = strassen::f32_tile_shape();
+        const Plan p = strassen::make_plan(m, n, k, levels, ks.vec);
+        std::memset(out, 0, sizeof(*out));
+        out->levels = levels;
+        out->blocks_per_dim = p.d;
+        out->sub_m = p.sm;
+        out->sub_n = p.sn;
+        out->sub_k = p.sk;
+        out->n_instances = (int32_t)p.products.size();
+        out->n_launches = (int32_t)p.batches.size();
+        out->tile_m = ks.mt;
+        out->tile_n = ks.nt;
+        out->tile_k = ks.kt;
+        out->workgroups_per_instance =
+            (int32_t)(((p.sm + ks.mt - 1) / ks.mt) * ((p.sn + ks.nt - 1) / ks.nt));
+        out->executed_flops = p.executed_flops;
+        out->classical_flops = 2.0 * (double)m * (double)n * (double)k;
+    } catch (...) {
+        return (int)hipErrorOutOfMemory;
+    }
+    return 0;
+}
+
+int strassen_plan_instances(int levels, strassen_instance_t *out, int capacity) {
+    if (levels < 0 || levels > STRASSEN_MAX_LEVELS) return -1;
+    if (out == nullptr && capacity > 0) return -2;
+    if (capacity < 0) return -3;
+    try {
+        // Block assignment does not depend on the matrix sizes.
+        const Plan p = strassen::make_plan(1 << levels, 1 << levels, 1 << levels, levels, 1);
+        int idx = 0;
+        for (size_t bi = 0; bi < p.batches.size(); ++bi)
+            for (int pi : p.batches[bi].products) {
+                if (idx < capacity) {
+                    const strassen::Product &q = p.products[pi];
+                    strassen_instance_t &o = out[idx];
+                    std::memset(&o, 0, sizeof(o));
+                    o.launch = (int32_t)bi;
+                    o.n_a = q.na;
+                    o.n_b = q.nb;
+                    o.n_c = q.nc;
+                    for (int t = 0; t < q.na; ++t) {
+                        o.a_block[t] = q.a[t].block;
+                        o.a_sign[t] = q.a[t].sign;
+                    }
+                    for (int t = 0; t < q.nb; ++t) {
+                        o.b_block[t] = q.b[t].block;
+                        o.b_sign[t] = q.b[t].sign;
+                    }
+                    for (int t = 0; t < q.nc; ++t) {
+                        o.c_block[t] = q.c[t].block;
+                        o.c_sign[t] = q.c[t].sign;
+                        o.c_first[t] = q.c_first[t] ? 1 : 0;
+                    }
+                }
+                ++idx;
+            }
+        return idx;
+    } catch (...) {
+        return (int)hipErrorOutOfMemory;
+    }
+}
+
+const char *strassen_error_string(int code) {
+    if (code == 0) return "success";
+    if (code < 0) {
+        const int i = -code;
+        if (i >= 1 && i <= (int)(sizeof(kArgMessages) / sizeof(kArgMessages[0])))
+            return kArgMessages[i - 1];
+        return "invalid argument";
+    }
+    const char *s = hipGetErrorString((hipError_t)code);
+    return s ? s : "HIP runtime error";
+}
+
+int strassen_profile_start(void) {
+    Recorder &r = recorder();
+    std::lock_guard<std::mutex> lk(r.mu);
+    for (Record &x : r.recs) {
+        r.pool.push_back(x.e0);
+        r.pool.push_back(x.e1);
+    }
+    r.recs.clear();
+    r.total = 0;
+    r.on = true;
+    return 0;
+}
+
+int strassen_profile_stop(strassen_launch_record_t *out, int capacity) {
+    if (out == nullptr && capacity > 0) return -1;
+    if (capacity < 0) return -2;
+    Recorder &r = recorder();
+    std::lock_guard<std::mutex> lk(r.mu);
+    r.on = false;
+    int idx = 0;
+    for (Record &x : r.recs) {
+        hipError_t err = hipEventSynchronize(x.e1);
+        if (err != hipSuccess) return (int)err;
+        float ms = 0.f;
+        err = hipEventElapsedTime(&ms, x.e0, x.e1);
+        if (err != hipSuccess) return (int)err;
+        x.info.ms = ms;
+        if (idx < capacity) out[idx] = x.info;
+        ++idx;
+    }
+    for (Record &x : r.recs) {
+        r.pool.push_back(x.e0);
+        r.pool.push_back(x.e1);
+    }
+    r.recs.clear();
+    const int total = r.total;
+    r.total = 0;
+    return total;
+}
+
+}  // extern "C"

@@ -1,0 +1,25 @@
+// Entry points of the device code, called by the C ABI (api.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernel_args.hpp"
+
+namespace strassen {
+
+struct KernelShape {
+    int mt, nt, kt;  // workgroup tile
+    int vec;         // elements per vector load along k (A) and n (B)
+};
+
+// fp32 operands, fp32 MFMA.  Launches one batch of `batch` products of
+// variant (wa, wb, wc); vec = 16-byte loads are aligned (see api.cpp).
+KernelShape f32_tile_shape();
+hipError_t launch_f32(int wa, int wb, int wc, const LaunchArgs &a, int batch, bool vec,
+                      hipStream_t s);
+const char *f32_kernel_name();
+
+// C := beta * C over an m x n matrix (beta == 0 writes zeros, C not read).
+hipError_t launch_scale(float *C, int64_t ldc, int64_t m, int64_t n, float beta, hipStream_t s);
+
+}  // namespace strassen

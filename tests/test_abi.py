@@ -1,0 +1,118 @@
+"""The C-ABI library loads, exports every symbol its header declares, and
+validates arguments with the documented codes -- all without a GPU (no call
+here reaches a kernel launch)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1808_07984_amd as sg
+from paper_1808_07984_amd import _binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names += re.findall(r"\b(strassen_\w+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_header_symbols_exported_and_bound():
+    names = _declared_functions()
+    assert "strassen_gemm" in names and "strassen_gemm_ex" in names
+    lib = ctypes.CDLL(_binding.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in _binding.SIGNATURES, name
+        assert hasattr(sg, name), name
+
+
+def test_no_oracle_in_product_path():
+    """The product package neither imports nor loads the oracle."""
+    pkg = os.path.join(ROOT, "paper_1808_07984_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".hpp", ".h")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in src and "from oracle" not in src, f
+                assert "liboracle" not in src, f
+
+
+N = None  # null pointer
+P = 4096  # any non-null value: validation rejects before anything is dereferenced
+
+
+@pytest.mark.parametrize("args,code", [
+    ((-1, 4, 4, P, 4, P, 4, P, 4, 1.0, 1.0, 1), -1),
+    ((4, -1, 4, P, 4, P, 4, P, 4, 1.0, 1.0, 1), -2),
+    ((4, 4, -1, P, 4, P, 4, P, 4, 1.0, 1.0, 1), -3),
+    ((4, 4, 4, N, 4, P, 4, P, 4, 1.0, 1.0, 1), -4),
+    ((4, 4, 8, P, 7, P, 4, P, 4, 1.0, 1.0, 1), -5),
+    ((4, 4, 4, P, 4, N, 4, P, 4, 1.0, 1.0, 1), -6),
+    ((4, 8, 4, P, 4, P, 7, P, 8, 1.0, 1.0, 1), -7),
+    ((4, 4, 4, P, 4, P, 4, N, 4, 1.0, 1.0, 1), -8),
+    ((4, 8, 4, 1 << 20, 4, 1 << 21, 8, P, 7, 1.0, 1.0, 1), -9),
+    ((4, 4, 4, 1 << 20, 4, 1 << 21, 4, P, 4, 1.0, 1.0, 3), -12),
+    ((4, 4, 4, 1 << 20, 4, 1 << 21, 4, P, 4, 1.0, 1.0, -1), -12),
+    # A overlaps C
+    ((4, 4, 4, 1 << 20, 4, 1 << 21, 4, (1 << 20) + 16, 4, 1.0, 1.0, 1), -8),
+    # B overlaps C
+    ((4, 4, 4, 1 << 20, 4, 1 << 21, 4, (1 << 21) - 8, 4, 1.0, 1.0, 1), -8),
+    # m == 0 / n == 0: nothing to do, success without touching the GPU
+    ((0, 4, 4, N, 4, N, 4, N, 4, 1.0, 1.0, 1), 0),
+    ((4, 0, 4, N, 4, N, 4, N, 4, 1.0, 1.0, 1), 0),
+])
+def test_strassen_gemm_validation(args, code):
+    assert sg.strassen_gemm(*args) == code
+
+
+def test_ex_validation():
+    base = dict(m=4, n=4, k=4, A=1 << 20, lda=4, a_type=0, trans_a=0, B=1 << 21, ldb=4, b_type=0,
+                trans_b=0, C=1 << 22, ldc=4, alpha=1.0, beta=1.0, levels=1, mode=0, hip_stream=None)
+
+    def call(**kw):
+        a = dict(base, **kw)
+        return sg.strassen_gemm_ex(*a.values())
+
+    assert call(a_type=7) == -6
+    assert call(trans_a=2) == -7
+    assert call(b_type=1) == -10
+    assert call(trans_b=-1) == -11
+    assert call(ldc=3) == -13
+    assert call(levels=5) == -16
+    assert call(mode=9) == -17
+    assert call(mode=1, a_type=1, b_type=1) == -17   # compensated mode needs fp32 operands
+    assert call(trans_a=1, lda=3, m=4, k=4) == -5    # stored A is k x m
+    assert call(C=(1 << 20) + 4) == -12               # overlap reported on C
+
+
+def test_error_strings():
+    assert sg.strassen_error_string(0) == "success"
+    assert "argument 4" in sg.strassen_error_string(-4)
+    assert sg.strassen_error_string(-99) == "invalid argument"
+    assert isinstance(sg.strassen_error_string(1), str)
+
+
+def test_plan_info_validation():
+    rc, _ = sg.strassen_plan_info(-1, 1, 1, 1)
+    assert rc == -1
+    rc, _ = sg.strassen_plan_info(1, 1, 1, 3)
+    assert rc == -4
+    rc, _ = sg.strassen_plan_info(1, 1, 1, 1, 0, 1)
+    assert rc == 0
+    rc, _ = sg.strassen_plan_info(1, 1, 1, 1, 1, 1)
+    assert rc == -6
+    rc, _ = sg.strassen_plan_instances(3)
+    assert rc == -1
+
+
+def test_profile_records_nothing_without_launches():
+    assert sg.strassen_profile_start() == 0
+    rc, recs = sg.strassen_profile_stop()
+    assert rc == 0 and recs == []

@@ -1,0 +1,216 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.
+
+* integer inputs: Strassen equals the classical product exactly, so the GPU
+  result must be bit-identical to the oracle (all levels, ragged sizes);
+* real inputs: within tau_L * eps * (k |alpha| |A| |B| + |beta| |C|) of the
+  fp64 oracle (tests/parity.py);
+* fringes and memory safety: ld padding poisoned with NaN stays untouched,
+  guard rows around C are not written, beta = 0 ignores NaN in C, k = 0 and
+  alpha = 0 give beta*C, sizes below 2^levels;
+* determinism (no atomics) and zero device allocation by the library;
+* the full sizes of the benchmark workloads, on sampled entries.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1808_07984_amd as sg
+from paper_1808_07984_amd import inputs
+from parity import EPS, e_norm, make_problem, tau, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(prob, levels, alpha, beta, mode="plain"):
+    dev = to_device(prob)
+    print("case m=%d n=%d k=%d L=%d alpha=%g beta=%g dtype=%s mode=%s" % (
+        prob["A"].shape[0], prob["B"].shape[1], prob["A"].shape[1], levels, alpha, beta,
+        prob["A"].dtype, mode), flush=True)
+    sg.gemm(dev["A"], dev["B"], dev["C"], alpha=alpha, beta=beta, levels=levels, mode=mode)
+    torch.cuda.synchronize()
+    return dev
+
+
+@pytest.mark.parametrize("levels", [0, 1, 2])
+@pytest.mark.parametrize("m,n,k", [(64, 64, 64), (65, 67, 63), (200, 129, 77), (3, 5, 7),
+                                   (1, 1, 1), (257, 130, 300)])
+def test_integer_exact(m, n, k, levels):
+    prob = make_problem(m, n, k, kind="integers", c_kind="integers")
+    dev = _run(prob, levels, 1.0, 1.0)
+    want = oracle.gemm_f64(prob["A"], prob["B"], prob["C"], 1.0, 1.0)
+    got = dev["C"].cpu().double().numpy()
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_integer_exact_alpha_beta_padded(levels):
+    """alpha = 1.5, beta = 0.5 (exact on integers), padded leading dimensions
+    with NaN in the padding, which must stay NaN and never leak in."""
+    m, n, k = 375, 501, 313
+    prob = make_problem(m, n, k, kind="integers", c_kind="integers",
+                        lda=k + 11, ldb=n + 9, ldc=n + 7)
+    dev = _run(prob, levels, 1.5, 0.5)
+    want = oracle.gemm_f64(prob["A"], prob["B"], prob["C"], 1.5, 0.5)
+    assert np.array_equal(dev["C"].cpu().double().numpy(), want)
+    pad = dev["C_storage"][:, n:].cpu()
+    assert torch.isnan(pad).all()
+
+
+@pytest.mark.parametrize("levels", [0, 1, 2])
+@pytest.mark.parametrize("m,n,k", [(1024, 1024, 1024), (1000, 1100, 900), (384, 256, 2048)])
+def test_float_within_tolerance(m, n, k, levels):
+    prob = make_problem(m, n, k, kind="uniform", c_kind="uniform")
+    dev = _run(prob, levels, 1.0, 1.0)
+    want = oracle.gemm_f64(prob["A"], prob["B"], prob["C"], 1.0, 1.0)
+    got = dev["C"].cpu().double().numpy()
+    en = e_norm(got, want, prob["A"], prob["B"], prob["C"], k, 1.0, 1.0, EPS["f32"])
+    print("e_norm=%.4f (tau=%g)" % (en, tau(levels)), flush=True)
+    assert en <= tau(levels)
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_float_matches_f32_emulation_level(levels):
+    """The GPU error is of the size the binary32 emulation of the same scheme
+    predicts (within a factor 8), not merely inside the tolerance."""
+    n = 512
+    prob = make_problem(n, n, n, kind="uniform", c_kind="zeros")
+    dev = _run(prob, levels, 1.0, 0.0)
+    exact = oracle.gemm_f64(prob["A"], prob["B"])
+    emu = oracle.strassen(prob["A"], prob["B"], levels=levels, f32emu=True)
+    err_gpu = np.abs(dev["C"].cpu().double().numpy() - exact).max()
+    err_emu = np.abs(emu - exact).max()
+    print("err gpu %.3e emu %.3e" % (err_gpu, err_emu), flush=True)
+    assert err_gpu <= 8 * err_emu + 1e-30
+
+
+def test_guard_rows_untouched():
+    """C is a window inside a larger buffer: rows above/below and columns
+    outside the window keep their values."""
+    m, n, k = 300, 260, 200
+    prob = make_problem(m, n, k, kind="integers", c_kind="integers")
+    big = torch.full((m + 8, n + 16), 7.0, device="cuda")
+    C = big[4:4 + m, 8:8 + n]
+    C.copy_(prob["C"].cuda())
+    A, B = prob["A"].cuda(), prob["B"].cuda()
+    for L in (0, 1, 2):
+        C.copy_(prob["C"].cuda())
+        sg.gemm(A, B, C, 1.0, 1.0, levels=L)
+        torch.cuda.synchronize()
+        want = oracle.gemm_f64(prob["A"], prob["B"], prob["C"], 1.0, 1.0)
+        assert np.array_equal(C.cpu().double().numpy(), want)
+        host = big.cpu()
+        mask = torch.ones_like(host, dtype=torch.bool)
+        mask[4:4 + m, 8:8 + n] = False
+        assert (host[mask] == 7.0).all(), L
+
+
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_beta_zero_ignores_nan(levels):
+    prob = make_problem(130, 70, 90, kind="integers", c_kind="zeros")
+    prob["C"] = torch.full((130, 70), float("nan"))
+    dev = _run(prob, levels, 1.0, 0.0)
+    want = oracle.gemm_f64(prob["A"], prob["B"])
+    assert np.array_equal(dev["C"].cpu().double().numpy(), want)
+
+
+def test_k_zero_and_alpha_zero():
+    C0 = inputs.integers(33, 45, 2).cuda()
+    A = torch.empty(33, 0, device="cuda")
+    B = torch.empty(0, 45, device="cuda")
+    for L in (0, 1, 2):
+        C = C0.clone()
+        sg.gemm(A, B, C, 1.0, 2.0, levels=L)
+        torch.cuda.synchronize()
+        assert torch.equal(C, 2 * C0)
+    An = torch.full((33, 10), float("nan"), device="cuda")
+    Bn = torch.full((10, 45), float("nan"), device="cuda")
+    C = C0.clone()
+    sg.gemm(An, Bn, C, 0.0, 0.5, levels=2)
+    torch.cuda.synchronize()
+    assert torch.equal(C, 0.5 * C0)
+    C = C0.clone()
+    sg.gemm(An, Bn, C, 0.0, 0.0, levels=1)
+    torch.cuda.synchronize()
+    assert torch.equal(C, torch.zeros_like(C0))
+
+
+def test_empty_outputs_untouched():
+    A = torch.ones(0, 5, device="cuda")
+    B = torch.ones(5, 4, device="cuda")
+    C = torch.ones(0, 4, device="cuda")
+    sg.gemm(A, B, C, 1.0, 1.0, levels=2)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_deterministic(levels):
+    prob = make_problem(700, 650, 600, kind="uniform", c_kind="uniform")
+    d1 = _run(prob, levels, 1.0, 1.0)
+    d2 = _run(prob, levels, 1.0, 1.0)
+    assert torch.equal(d1["C"], d2["C"])
+
+
+def test_no_device_allocation():
+    """The library allocates no workspace: free device memory is unchanged
+    across calls (E5 of the paper's memory-capacity discussion)."""
+    prob = make_problem(2048, 2048, 2048, kind="uniform", c_kind="uniform")
+    dev = to_device(prob)
+    sg.gemm(dev["A"], dev["B"], dev["C"], 1.0, 1.0, levels=2)  # loads the code object
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    for L in (0, 1, 2):
+        sg.gemm(dev["A"], dev["B"], dev["C"], 1.0, 1.0, levels=L)
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    assert free1 == free0
+
+
+def _sampled(m, n, k, levels, alpha, beta, lda=None, ldb=None, ldc=None, kind="uniform",
+             nsamp=512, exact=False):
+    """Full-size call, compared on sampled entries against oracle.gemm_entries."""
+    prob = make_problem(m, n, k, kind=kind, c_kind=kind, lda=lda, ldb=ldb, ldc=ldc,
+                        int_range=(-1, 1))
+    dev = _run(prob, levels, alpha, beta)
+    rng = np.random.default_rng(m + n + k + levels)
+    rows = np.concatenate([rng.integers(0, m, nsamp), [0, m - 1, m - 1, 0]])
+    cols = np.concatenate([rng.integers(0, n, nsamp), [0, n - 1, 0, n - 1]])
+    want = oracle.gemm_entries(prob["A"], prob["B"], prob["C"], rows, cols, alpha, beta)
+    Cg = dev["C"]
+    got = Cg[torch.as_tensor(rows, device="cuda"), torch.as_tensor(cols, device="cuda")].cpu().double().numpy()
+    if exact:
+        assert np.array_equal(got, want)
+    else:
+        amax = float(prob["A"].abs().max())
+        bmax = float(prob["B"].abs().max())
+        cmax = float(prob["C"].abs().max())
+        scale = k * abs(alpha) * amax * bmax + abs(beta) * cmax
+        en = float(np.abs(got - want).max()) / (EPS["f32"] * scale)
+        print("sampled e_norm=%.4f (tau=%g)" % (en, tau(levels)), flush=True)
+        assert en <= tau(levels)
+    assert bool(torch.isfinite(Cg).all())
+    if ldc and ldc > n:
+        assert bool(torch.isnan(dev["C_storage"][:, n:]).all())
+
+
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_full_size_square_16384(levels):
+    _sampled(16384, 16384, 16384, levels, 1.0, 1.0)
+
+
+@pytest.mark.parametrize("levels", [2])
+def test_full_size_awkward_15001(levels):
+    _sampled(15001, 17003, 9007, levels, 1.5, 0.5, lda=9024, ldb=17024, ldc=17024)
+
+
+@pytest.mark.parametrize("levels", [2])
+def test_full_size_awkward_3000(levels):
+    _sampled(3000, 20000, 5000, levels, 1.5, 0.5, lda=5056, ldb=20032, ldc=20032)
+
+
+def test_full_size_awkward_integer_exact():
+    """Entries in {-1, 0, 1}: exact at every sampled entry (largest
+    intermediate well below 2^23)."""
+    _sampled(15001, 17003, 9007, 2, 1.5, 0.5, lda=9024, ldb=17024, ldc=17024,
+             kind="integers", exact=True)
