@@ -78,7 +78,32 @@ SIGNATURES = {
 }
 
 
+def _hip_runtimes():
+    """Distinct libamdhip64 files mapped into this process (Linux)."""
+    try:
+        with open("/proc/self/maps") as f:
+            return sorted({ln.split()[-1] for ln in f if "libamdhip64" in ln and "/" in ln})
+    except OSError:
+        return []
+
+
+def check_single_hip_runtime():
+    """A process must hold one HIP runtime: a second copy cannot open the GPU
+    and reports "no ROCm-capable device".  Raises if two are mapped."""
+    libs = _hip_runtimes()
+    if len(libs) > 1:
+        raise RuntimeError("two HIP runtimes are loaded (%s); import torch before this "
+                           "package so libstrassen.so binds to torch's runtime" % ", ".join(libs))
+
+
 def _load():
+    # torch ships its own libamdhip64 (soname libamdhip64.so.7) and loads it by
+    # the unversioned name.  Importing torch first makes the dynamic linker
+    # resolve libstrassen.so's libamdhip64.so.7 to that same copy.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             "libstrassen.so is not built (%s); run `python -m paper_1808_07984_amd.build`" % LIB_PATH)
@@ -87,6 +112,7 @@ def _load():
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
+    check_single_hip_runtime()
     return lib
 
 
