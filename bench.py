@@ -26,6 +26,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP32_MFMA_PEAK = 157.3  # TFLOP/s, MI355X dense fp32 matrix peak
+BF16_MFMA_PEAK = 2516.6  # TFLOP/s, MI355X dense bf16/fp16 matrix peak
 
 
 def log(*a):
@@ -41,6 +42,8 @@ def parse():
     p.add_argument("--size", type=int, default=16384)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--no-precision", action="store_true",
+                   help="skip the bf16 / fp16 / bf16x3 section")
     return p.parse_args()
 
 
@@ -72,6 +75,72 @@ def cpu_baseline(A, B, C, target_s):
     return {"value": flops / t / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
             "sample": "classical fp64 oracle_gemm_f64 on the first %d of %d rows of C = A*B + C "
                       "(n = k = %d), %.1f s" % (rows, A.shape[0], n, t)}
+
+
+def time_calls(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def precision_section(N, steps, dev, stream, log):
+    """bf16 and fp16 operands and the compensated bf16x3 mode at m=n=k=N,
+    N(0,1) inputs, beta = 0: effective TFLOP/s per level and the sampled
+    error against the fp64 oracle on the stored operands."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_1808_07984_amd as sg
+    from paper_1808_07984_amd import inputs
+
+    A32 = inputs.normal(N, N, inputs.SEED_A)
+    B32 = inputs.normal(N, N, inputs.SEED_B)
+    rng = np.random.default_rng(1)
+    rows, cols = rng.integers(0, N, 256), rng.integers(0, N, 256)
+    ri, ci = torch.as_tensor(rows, device=dev), torch.as_tensor(cols, device=dev)
+    out = {}
+    for name, tdt, mode, eps_gate in (("bf16", torch.bfloat16, "plain", 2.0 ** -7),
+                                      ("f16", torch.float16, "plain", 2.0 ** -10),
+                                      ("bf16x3", torch.float32, "bf16x3", 2.0 ** -16)):
+        Ah, Bh = A32.to(tdt), B32.to(tdt)
+        want = oracle.gemm_entries(Ah, Bh, None, rows, cols, 1.0, 0.0)
+        scale = N * float(Ah.float().abs().max()) * float(Bh.float().abs().max())
+        A, B = Ah.to(dev), Bh.to(dev)
+        C = torch.zeros(N, N, device=dev)
+        res = {}
+        for L in (0, 1, 2):
+            def call():
+                sg.gemm(A, B, C, 1.0, 0.0, levels=L, mode=mode)
+            call()
+            torch.cuda.synchronize()
+            got = C[ri, ci].double().cpu().numpy()
+            err = float(np.abs(got - want).max())
+            ms = time_calls(call, steps, 1, stream)
+            info = sg.plan_info(N, N, N, L, tdt, mode)
+            mult = 3.0 if mode == "bf16x3" else 1.0
+            eff = 2.0 * N ** 3 / (ms * 1e-3) / 1e12
+            exe = mult * info.executed_flops / (ms * 1e-3) / 1e12
+            res["L%d" % L] = {"ms_per_step": round(ms, 4), "effective_tflops": round(eff, 2),
+                              "executed_mfma_tflops": round(exe, 2),
+                              "mfma_frac_executed": round(exe / BF16_MFMA_PEAK, 4),
+                              "e_norm_eps23": round(err / (2.0 ** -23 * scale), 3),
+                              "e_norm_gate": round(err / (eps_gate * scale), 4),
+                              "gate_eps": eps_gate, "tolerance": 2.0 ** (L + 1)}
+            log("%s L%d: %.3f ms  effective %.1f TFLOP/s  e_norm %.4f (gate eps %g)"
+                % (name, L, ms, eff, err / (eps_gate * scale), eps_gate))
+        out[name] = res
+        del A, B, C
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -169,6 +238,13 @@ def main():
                 "avg_launch_ms": round(dom_ms / dom_n, 4),
                 "flops_per_launch": dom_flops / dom_n}
 
+    precision = None
+    if not args.no_precision:
+        log("precision section: bf16, fp16, bf16x3 at m=n=k=%d" % N)
+        del C0
+        torch.cuda.empty_cache()
+        precision = precision_section(N, max(1, min(args.steps, 5)), dev, stream, log)
+
     head = per_level["L%d" % args.levels]
     result = {
         "metric": "effective TFLOP/s (2mnk/t) Strassen 1L/2L vs plain GEMM, m=n=k=16384",
@@ -190,6 +266,10 @@ def main():
         "parity_sampled_e_norm": parity,
         "roofline": roofline,
     }
+    if precision is not None:
+        result["precision"] = {"workload": "A,B ~ N(0,1) seeded, C := A*B (beta 0), m=n=k=%d; "
+                                           "errors on 256 sampled entries vs the fp64 oracle" % N,
+                               **precision}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(A_h, B_h, C_h, args.cpu_seconds)

@@ -19,7 +19,8 @@ OUT_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(OUT_DIR, "libstrassen.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "plan.cpp", "scale.hip", "gemm_f32.hip"]
+SOURCES = ["api.cpp", "plan.cpp", "scale.hip", "gemm_f32.hip", "gemm_bf16.hip",
+           "gemm_f16.hip", "gemm_bf16x3.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I" + INCLUDE, "-I" + CSRC]
 # Packed fp32 instructions are disabled for all device code.

@@ -121,9 +121,7 @@ int validate(const Call &c) {
         if (overlap(c.A, span_bytes(a_rows, a_cols, c.lda, es), c.C, nc)) return -12;
         if (overlap(c.B, span_bytes(b_rows, b_cols, c.ldb, es), c.C, nc)) return -12;
     }
-    // Not built yet: 16-bit operands, the compensated mode, transposed operands.
-    if (c.a_type != STRASSEN_F32) return -6;
-    if (c.mode != STRASSEN_MODE_PLAIN) return -17;
+    // Not built yet: transposed operands.
     if (c.trans_a) return -7;
     if (c.trans_b) return -11;
     return 0;
@@ -142,12 +140,32 @@ TermArg term(int64_t off, int64_t rows, int64_t cols, int sign, bool first) {
     return t;
 }
 
+// Kernel family of a call: fp32 MFMA, or the 16-bit MFMA path.
+struct Family {
+    bool m16;
+    strassen::Operand16 op;
+    strassen::KernelShape shape;
+    const char *name;
+};
+
+Family family(strassen_dtype_t t, strassen_mode_t mode) {
+    using strassen::Operand16;
+    if (t == STRASSEN_F32 && mode == STRASSEN_MODE_PLAIN)
+        return Family{false, Operand16::kBf16, strassen::f32_tile_shape(), strassen::f32_kernel_name()};
+    const Operand16 op = (t == STRASSEN_BF16) ? Operand16::kBf16
+                         : (t == STRASSEN_F16) ? Operand16::kF16
+                                               : Operand16::kBf16x3;
+    return Family{true, op, strassen::m16_tile_shape(op == Operand16::kBf16x3),
+                  strassen::m16_kernel_name(op)};
+}
+
 int run(const Call &c) {
     if (c.m == 0 || c.n == 0) return 0;
     if (c.k == 0 || c.alpha == 0.f)
         return (int)strassen::launch_scale(c.C, c.ldc, c.m, c.n, c.beta, c.stream);
 
-    const strassen::KernelShape ks = strassen::f32_tile_shape();
+    const Family fam = family(c.a_type, c.mode);
+    const strassen::KernelShape ks = fam.shape;
     const Plan plan = strassen::make_plan(c.m, c.n, c.k, c.levels, ks.vec);
     const int d = plan.d;
 
@@ -217,15 +235,17 @@ int run(const Call &c) {
             const hipError_t err = hipEventRecord(e0, c.stream);
             if (err != hipSuccess) return (int)err;
         }
-        const hipError_t err = strassen::launch_f32(bt.wa, bt.wb, bt.wc, a, batch, vec, c.stream);
+        const hipError_t err =
+            fam.m16 ? strassen::launch_m16(fam.op, bt.wa, bt.wb, bt.wc, a, batch, vec, c.stream)
+                    : strassen::launch_f32(bt.wa, bt.wb, bt.wc, a, batch, vec, c.stream);
         if (err != hipSuccess) return (int)err;
         if (timed) {
             const hipError_t e2 = hipEventRecord(e1, c.stream);
             if (e2 != hipSuccess) return (int)e2;
             Record r;
             std::memset(&r.info, 0, sizeof(r.info));
-            std::snprintf(r.info.kernel, sizeof(r.info.kernel), "%s<%d,%d,%d,%s>",
-                          strassen::f32_kernel_name(), bt.wa, bt.wb, bt.wc, vec ? "vec" : "scalar");
+            std::snprintf(r.info.kernel, sizeof(r.info.kernel), "%s<%d,%d,%d,%s>", fam.name,
+                          bt.wa, bt.wb, bt.wc, vec ? "vec" : "scalar");
             r.info.launch = (int32_t)bi;
             r.info.batch = batch;
             r.info.workgroups = a.tiles_m * a.tiles_n * batch;
@@ -309,7 +329,7 @@ int strassen_plan_info(int64_t m, int64_t n, int64_t k, int levels, strassen_dty
     if (mode == STRASSEN_MODE_BF16X3 && dtype != STRASSEN_F32) return -6;
     if (out == nullptr) return -7;
     try {
-        const strassen::KernelShape ks = strassen::f32_tile_shape();
+        const strassen::KernelShape ks = family(dtype, mode).shape;
         const Plan p = strassen::make_plan(m, n, k, levels, ks.vec);
         std::memset(out, 0, sizeof(*out));
         out->levels = levels;

@@ -19,6 +19,20 @@ hipError_t launch_f32(int wa, int wb, int wc, const LaunchArgs &a, int batch, bo
                       hipStream_t s);
 const char *f32_kernel_name();
 
+// 16-bit MFMA path: bf16 or fp16 operands, or fp32 operands split into
+// bf16 hi/lo pairs (compensated product hi*hi + hi*lo + lo*hi).
+enum class Operand16 { kBf16, kF16, kBf16x3 };
+KernelShape m16_tile_shape(bool x3);
+hipError_t launch_m16(Operand16 op, int wa, int wb, int wc, const LaunchArgs &a, int batch,
+                      bool vec, hipStream_t s);
+const char *m16_kernel_name(Operand16 op);
+hipError_t launch_m16_bf16(int wa, int wb, int wc, const LaunchArgs &a, int batch, bool vec,
+                           hipStream_t s);
+hipError_t launch_m16_f16(int wa, int wb, int wc, const LaunchArgs &a, int batch, bool vec,
+                          hipStream_t s);
+hipError_t launch_m16_bf16x3(int wa, int wb, int wc, const LaunchArgs &a, int batch, bool vec,
+                             hipStream_t s);
+
 // C := beta * C over an m x n matrix (beta == 0 writes zeros, C not read).
 hipError_t launch_scale(float *C, int64_t ldc, int64_t m, int64_t n, float beta, hipStream_t s);
 

@@ -1,0 +1,119 @@
+"""GPU parity of the 16-bit MFMA path: bf16 and fp16 operands (sums rounded
+once to the operand type), and the compensated bf16x3 mode on fp32 operands.
+
+* integer inputs: every operand sum (at most four terms of magnitude <= 3) and
+  every bf16 hi/lo split is exact, so the result equals the classical product
+  bit for bit;
+* real inputs: within tau_L * eps * (k |alpha| |A| |B| + |beta| |C|) of the
+  fp64 oracle evaluated on the exact stored operands, eps = 2^-7 (bf16),
+  2^-10 (fp16), 2^-16 (bf16x3: hi + lo carries 16 significant bits);
+* the compensated mode is far more accurate than plain bf16 on the same data.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1808_07984_amd as sg
+from parity import EPS, e_norm, make_problem, tau, to_device
+
+pytestmark = pytest.mark.gpu
+
+MODES = {"bf16": ("bf16", "plain"), "f16": ("f16", "plain"), "bf16x3": ("bf16x3", "bf16x3")}
+GATE_EPS = {"bf16": 2.0 ** -7, "f16": 2.0 ** -10, "bf16x3": 2.0 ** -16}
+
+
+def _run(prob, levels, alpha, beta, mode):
+    dev = to_device(prob)
+    print("case m=%d n=%d k=%d L=%d dtype=%s mode=%s" % (
+        prob["A"].shape[0], prob["B"].shape[1], prob["A"].shape[1], levels, prob["A"].dtype, mode),
+        flush=True)
+    sg.gemm(dev["A"], dev["B"], dev["C"], alpha=alpha, beta=beta, levels=levels, mode=mode)
+    torch.cuda.synchronize()
+    return dev
+
+
+@pytest.mark.parametrize("kind", sorted(MODES))
+@pytest.mark.parametrize("levels", [0, 1, 2])
+@pytest.mark.parametrize("m,n,k", [(64, 64, 64), (65, 67, 63), (200, 129, 77), (3, 5, 7),
+                                   (257, 130, 300)])
+def test_lowp_integer_exact(kind, levels, m, n, k):
+    dtype, mode = MODES[kind]
+    prob = make_problem(m, n, k, kind="integers", dtype=dtype, c_kind="integers")
+    dev = _run(prob, levels, 1.0, 1.0, mode)
+    want = oracle.gemm_f64(prob["A"], prob["B"], prob["C"], 1.0, 1.0)
+    assert np.array_equal(dev["C"].cpu().double().numpy(), want)
+
+
+@pytest.mark.parametrize("kind", sorted(MODES))
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_lowp_integer_exact_padded_alpha_beta(kind, levels):
+    dtype, mode = MODES[kind]
+    m, n, k = 375, 501, 313
+    prob = make_problem(m, n, k, kind="integers", dtype=dtype, c_kind="integers",
+                        lda=k + 11, ldb=n + 9, ldc=n + 7)
+    dev = _run(prob, levels, 1.5, 0.5, mode)
+    want = oracle.gemm_f64(prob["A"], prob["B"], prob["C"], 1.5, 0.5)
+    assert np.array_equal(dev["C"].cpu().double().numpy(), want)
+    assert torch.isnan(dev["C_storage"][:, n:]).all()
+
+
+@pytest.mark.parametrize("kind", sorted(MODES))
+@pytest.mark.parametrize("levels", [0, 1, 2])
+@pytest.mark.parametrize("m,n,k", [(512, 384, 640), (1000, 1100, 900)])
+def test_lowp_float_within_tolerance(kind, levels, m, n, k):
+    dtype, mode = MODES[kind]
+    dist = "uniform" if kind == "bf16x3" else "normal"
+    prob = make_problem(m, n, k, kind=dist, dtype=dtype, c_kind="uniform")
+    dev = _run(prob, levels, 1.0, 1.0, mode)
+    want = oracle.gemm_f64(prob["A"], prob["B"], prob["C"], 1.0, 1.0)
+    got = dev["C"].cpu().double().numpy()
+    en = e_norm(got, want, prob["A"], prob["B"], prob["C"], k, 1.0, 1.0, GATE_EPS[kind])
+    en23 = e_norm(got, want, prob["A"], prob["B"], prob["C"], k, 1.0, 1.0, EPS["f32"])
+    print("e_norm=%.4f at eps=%g (tau=%g); %.3f at 2^-23" % (en, GATE_EPS[kind], tau(levels), en23),
+          flush=True)
+    assert en <= tau(levels)
+
+
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_bf16x3_far_more_accurate_than_bf16(levels):
+    """Same fp32 operands: the compensated mode's error is at least 32x below
+    plain bf16 on the bf16-rounded operands."""
+    m = n = k = 768
+    prob = make_problem(m, n, k, kind="uniform", dtype="bf16x3", c_kind="zeros")
+    exact = oracle.gemm_f64(prob["A"], prob["B"])
+    d3 = _run(prob, levels, 1.0, 0.0, "bf16x3")
+    err3 = np.abs(d3["C"].cpu().double().numpy() - exact).max()
+    pb = dict(prob, A=prob["A"].to(torch.bfloat16), B=prob["B"].to(torch.bfloat16))
+    db = _run(pb, levels, 1.0, 0.0, "plain")
+    errb = np.abs(db["C"].cpu().double().numpy() - exact).max()
+    print("err bf16x3 %.3e  bf16 %.3e" % (err3, errb), flush=True)
+    assert err3 * 32 <= errb
+
+
+def test_lowp_deterministic():
+    prob = make_problem(600, 520, 700, kind="normal", dtype="bf16", c_kind="uniform")
+    d1 = _run(prob, 2, 1.0, 1.0, "plain")
+    d2 = _run(prob, 2, 1.0, 1.0, "plain")
+    assert torch.equal(d1["C"], d2["C"])
+
+
+@pytest.mark.parametrize("kind,levels", [("bf16", 2), ("f16", 1), ("bf16x3", 2)])
+def test_lowp_full_size_sampled(kind, levels):
+    """m = n = k = 16384 (the precision configuration's largest size), sampled
+    entries against the classical fp64 definition on the stored operands."""
+    dtype, mode = MODES[kind]
+    N = 16384
+    dist = "uniform" if kind == "bf16x3" else "normal"
+    prob = make_problem(N, N, N, kind=dist, dtype=dtype, c_kind="zeros")
+    dev = _run(prob, levels, 1.0, 0.0, mode)
+    rng = np.random.default_rng(levels)
+    rows, cols = rng.integers(0, N, 400), rng.integers(0, N, 400)
+    want = oracle.gemm_entries(prob["A"], prob["B"], None, rows, cols, 1.0, 0.0)
+    got = dev["C"][torch.as_tensor(rows, device="cuda"),
+                   torch.as_tensor(cols, device="cuda")].double().cpu().numpy()
+    scale = N * float(prob["A"].float().abs().max()) * float(prob["B"].float().abs().max())
+    en = float(np.abs(got - want).max()) / (GATE_EPS[kind] * scale)
+    print("sampled e_norm %.4f at eps=%g" % (en, GATE_EPS[kind]), flush=True)
+    assert en <= tau(levels)
+    assert bool(torch.isfinite(dev["C"]).all())
