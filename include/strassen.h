@@ -103,6 +103,15 @@ int strassen_gemm_ex(int64_t m, int64_t n, int64_t k,
  * NULL = the null stream).  Always returns 0. */
 int strassen_set_stream(void *hip_stream);
 
+/* Workgroup tile of the fp32 kernels.  AUTO (the default) picks 256x256 when
+ * every product of a launch has at least 128 such tiles and the launch at
+ * least 256, else 128x128; the others force one shape for every fp32 launch
+ * (tuning, tests).  Process-wide; returns 0 or -1 (bad value). */
+#define STRASSEN_TILE_AUTO 0
+#define STRASSEN_TILE_128 1
+#define STRASSEN_TILE_256 2
+int strassen_set_tile(int tile);
+
 /* Description of how a call of this shape is executed. */
 typedef struct {
     int32_t levels;            /* 0, 1 or 2 */

@@ -22,6 +22,9 @@ from ._binding import (  # noqa: F401
     STRASSEN_MAX_LEVELS,
     STRASSEN_MODE_BF16X3,
     STRASSEN_MODE_PLAIN,
+    STRASSEN_TILE_128,
+    STRASSEN_TILE_256,
+    STRASSEN_TILE_AUTO,
     StrassenError,
     strassen_error_string,
     strassen_gemm,
@@ -31,5 +34,7 @@ from ._binding import (  # noqa: F401
     strassen_profile_start,
     strassen_profile_stop,
     strassen_set_stream,
+    strassen_set_tile,
 )
 from .api import gemm, plan_info  # noqa: F401
+from .autograd import StrassenMatmul, strassen_matmul  # noqa: F401

@@ -1,7 +1,7 @@
 """ctypes binding of libstrassen.so: the C ABI of include/strassen.h with the
 same names, argument marshalling only.
 
-The library must have been built (``python -m paper_1808_07984_amd.build`` or
+The library must have been built (``python paper_1808_07984_amd/build.py`` or
 ``__graft_entry__.build()``); importing this module without it raises, there
 is no fallback path.
 """
@@ -69,6 +69,7 @@ SIGNATURES = {
     "strassen_gemm_ex": (_int, [_i64, _i64, _i64, _vp, _i64, _int, _int, _vp, _i64, _int, _int,
                                 _vp, _i64, _f32, _f32, _int, _int, _vp]),
     "strassen_set_stream": (_int, [_vp]),
+    "strassen_set_tile": (_int, [_int]),
     "strassen_plan_info": (_int, [_i64, _i64, _i64, _int, _int, _int,
                                   ctypes.POINTER(strassen_plan_info_t)]),
     "strassen_plan_instances": (_int, [_int, ctypes.POINTER(strassen_instance_t), _int]),
@@ -106,7 +107,7 @@ def _load():
         pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(
-            "libstrassen.so is not built (%s); run `python -m paper_1808_07984_amd.build`" % LIB_PATH)
+            "libstrassen.so is not built (%s); run `python paper_1808_07984_amd/build.py`" % LIB_PATH)
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
@@ -139,6 +140,13 @@ def strassen_gemm_ex(m, n, k, A, lda, a_type, trans_a, B, ldb, b_type, trans_b, 
 
 def strassen_set_stream(hip_stream):
     return lib.strassen_set_stream(hip_stream)
+
+
+STRASSEN_TILE_AUTO, STRASSEN_TILE_128, STRASSEN_TILE_256 = 0, 1, 2
+
+
+def strassen_set_tile(tile):
+    return lib.strassen_set_tile(tile)
 
 
 def strassen_plan_info(m, n, k, levels, dtype=STRASSEN_F32, mode=STRASSEN_MODE_PLAIN):

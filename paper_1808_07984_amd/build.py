@@ -1,6 +1,8 @@
 """Builds the HIP library libstrassen.so for gfx950, in-tree.
 
-    python -m paper_1808_07984_amd.build      (or __graft_entry__.build())
+    python paper_1808_07984_amd/build.py      (or __graft_entry__.build())
+
+(Run it as a script: importing the package would first load the library.)
 
 Every source is compiled by hipcc (device code for gfx950 only) in parallel,
 then linked into paper_1808_07984_amd/_build/libstrassen.so, which the Python
@@ -19,8 +21,9 @@ OUT_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(OUT_DIR, "libstrassen.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "plan.cpp", "scale.hip", "gemm_f32.hip", "gemm_bf16.hip",
-           "gemm_f16.hip", "gemm_bf16x3.hip"]
+SOURCES = ["api.cpp", "plan.cpp", "scale.hip", "gemm_f32_dispatch.cpp", "gemm_bf16.hip",
+           "gemm_f16.hip", "gemm_bf16x3.hip"] + [
+    "gemm_f32_%s_%s.hip" % (lay, tile) for lay in ("nn", "nt", "tn", "tt") for tile in ("s", "l")]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I" + INCLUDE, "-I" + CSRC]
 # Packed fp32 instructions are disabled for all device code.

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -121,9 +122,10 @@ int validate(const Call &c) {
         if (overlap(c.A, span_bytes(a_rows, a_cols, c.lda, es), c.C, nc)) return -12;
         if (overlap(c.B, span_bytes(b_rows, b_cols, c.ldb, es), c.C, nc)) return -12;
     }
-    // Not built yet: transposed operands.
-    if (c.trans_a) return -7;
-    if (c.trans_b) return -11;
+    // Not built yet: transposed operands on the 16-bit path.
+    const bool m16 = c.a_type != STRASSEN_F32 || c.mode != STRASSEN_MODE_PLAIN;
+    if (m16 && c.trans_a) return -7;
+    if (m16 && c.trans_b) return -11;
     return 0;
 }
 
@@ -140,23 +142,43 @@ TermArg term(int64_t off, int64_t rows, int64_t cols, int sign, bool first) {
     return t;
 }
 
+// Tile choice of the fp32 kernels (strassen_set_tile): automatic, or forced
+// to 128x128 / 256x256 for tuning and testing.
+std::atomic<int> g_tile{STRASSEN_TILE_AUTO};
+
+bool use_large_f32(int wa, int wb, int64_t sm, int64_t sn, int batch) {
+    (void)wa;
+    (void)wb;
+    const int mode = g_tile.load(std::memory_order_relaxed);
+    if (mode == STRASSEN_TILE_128) return false;
+    if (mode == STRASSEN_TILE_256) return true;
+    // Measured on MI355X (fp32, levels 0-2, m = n = k = 8192 and 16384): the
+    // 256x256 tile is faster whenever each product still has >= 128 such
+    // tiles and the launch >= 256 (one per CU); below that the 128x128 tile's
+    // two workgroups per CU hide more latency.
+    const int64_t per_product = ((sm + 255) / 256) * ((sn + 255) / 256);
+    return per_product >= 128 && per_product * batch >= 256;
+}
+
 // Kernel family of a call: fp32 MFMA, or the 16-bit MFMA path.
 struct Family {
     bool m16;
     strassen::Operand16 op;
-    strassen::KernelShape shape;
-    const char *name;
+    int vec;  // elements per aligned vector load
 };
 
 Family family(strassen_dtype_t t, strassen_mode_t mode) {
     using strassen::Operand16;
-    if (t == STRASSEN_F32 && mode == STRASSEN_MODE_PLAIN)
-        return Family{false, Operand16::kBf16, strassen::f32_tile_shape(), strassen::f32_kernel_name()};
+    if (t == STRASSEN_F32 && mode == STRASSEN_MODE_PLAIN) return Family{false, Operand16::kBf16, 4};
     const Operand16 op = (t == STRASSEN_BF16) ? Operand16::kBf16
                          : (t == STRASSEN_F16) ? Operand16::kF16
                                                : Operand16::kBf16x3;
-    return Family{true, op, strassen::m16_tile_shape(op == Operand16::kBf16x3),
-                  strassen::m16_kernel_name(op)};
+    return Family{true, op, strassen::m16_tile_shape(op == Operand16::kBf16x3).vec};
+}
+
+strassen::KernelShape shape_of(const Family &f, bool large) {
+    return f.m16 ? strassen::m16_tile_shape(f.op == strassen::Operand16::kBf16x3)
+                 : strassen::f32_tile_shape(large);
 }
 
 int run(const Call &c) {
@@ -165,8 +187,7 @@ int run(const Call &c) {
         return (int)strassen::launch_scale(c.C, c.ldc, c.m, c.n, c.beta, c.stream);
 
     const Family fam = family(c.a_type, c.mode);
-    const strassen::KernelShape ks = fam.shape;
-    const Plan plan = strassen::make_plan(c.m, c.n, c.k, c.levels, ks.vec);
+    const Plan plan = strassen::make_plan(c.m, c.n, c.k, c.levels, fam.vec, c.trans_a != 0);
     const int d = plan.d;
 
     LaunchArgs a;
@@ -180,35 +201,41 @@ int run(const Call &c) {
     a.sm = (int32_t)plan.sm;
     a.sn = (int32_t)plan.sn;
     a.sk = (int32_t)plan.sk;
-    a.tiles_m = (int32_t)((plan.sm + ks.mt - 1) / ks.mt);
-    a.tiles_n = (int32_t)((plan.sn + ks.nt - 1) / ks.nt);
     a.alpha = c.alpha;
     a.beta = c.beta;
     a.trans_a = c.trans_a;
     a.trans_b = c.trans_b;
 
     // 16-byte loads need aligned bases, leading dimensions and block offsets
-    // (make_plan rounds block extents along n and k to the vector width).
-    const bool vec = (c.lda % ks.vec == 0) && (c.ldb % ks.vec == 0) &&
+    // (make_plan rounds block extents to the vector width).
+    const bool vec = (c.lda % fam.vec == 0) && (c.ldb % fam.vec == 0) &&
                      ((uintptr_t)c.A % 16 == 0) && ((uintptr_t)c.B % 16 == 0);
 
     Recorder &rec = recorder();
     for (size_t bi = 0; bi < plan.batches.size(); ++bi) {
         const strassen::Batch &bt = plan.batches[bi];
         const int batch = (int)bt.products.size();
+        const bool large = !fam.m16 && use_large_f32(bt.wa, bt.wb, plan.sm, plan.sn, batch);
+        const strassen::KernelShape ks = shape_of(fam, large);
+        a.tiles_m = (int32_t)((plan.sm + ks.mt - 1) / ks.mt);
+        a.tiles_n = (int32_t)((plan.sn + ks.nt - 1) / ks.nt);
         for (int z = 0; z < batch; ++z) {
             const strassen::Product &p = plan.products[bt.products[z]];
             ProductArg &pa = a.prod[z];
+            // Block (R, Cc) of op(X) starts at row R, column Cc of the block
+            // grid; a transposed operand stores it at column R, row Cc.
             for (int t = 0; t < p.na; ++t) {
                 const int R = p.a[t].block / d, Cc = p.a[t].block % d;
-                pa.a[t] = term(R * plan.sm * c.lda + Cc * plan.sk,
-                               strassen::block_extent(c.m, plan.sm, R),
+                const int64_t off = c.trans_a ? Cc * plan.sk * c.lda + R * plan.sm
+                                              : R * plan.sm * c.lda + Cc * plan.sk;
+                pa.a[t] = term(off, strassen::block_extent(c.m, plan.sm, R),
                                strassen::block_extent(c.k, plan.sk, Cc), p.a[t].sign, false);
             }
             for (int t = 0; t < p.nb; ++t) {
                 const int R = p.b[t].block / d, Cc = p.b[t].block % d;
-                pa.b[t] = term(R * plan.sk * c.ldb + Cc * plan.sn,
-                               strassen::block_extent(c.k, plan.sk, R),
+                const int64_t off = c.trans_b ? Cc * plan.sn * c.ldb + R * plan.sk
+                                              : R * plan.sk * c.ldb + Cc * plan.sn;
+                pa.b[t] = term(off, strassen::block_extent(c.k, plan.sk, R),
                                strassen::block_extent(c.n, plan.sn, Cc), p.b[t].sign, false);
             }
             for (int t = 0; t < p.nc; ++t) {
@@ -237,15 +264,19 @@ int run(const Call &c) {
         }
         const hipError_t err =
             fam.m16 ? strassen::launch_m16(fam.op, bt.wa, bt.wb, bt.wc, a, batch, vec, c.stream)
-                    : strassen::launch_f32(bt.wa, bt.wb, bt.wc, a, batch, vec, c.stream);
+                    : strassen::launch_f32(c.trans_a != 0, c.trans_b != 0, large, bt.wa, bt.wb,
+                                           bt.wc, a, batch, vec, c.stream);
         if (err != hipSuccess) return (int)err;
         if (timed) {
             const hipError_t e2 = hipEventRecord(e1, c.stream);
             if (e2 != hipSuccess) return (int)e2;
             Record r;
             std::memset(&r.info, 0, sizeof(r.info));
-            std::snprintf(r.info.kernel, sizeof(r.info.kernel), "%s<%d,%d,%d,%s>", fam.name,
-                          bt.wa, bt.wb, bt.wc, vec ? "vec" : "scalar");
+            std::snprintf(r.info.kernel, sizeof(r.info.kernel), "%s<%d,%d,%d,%s%s%s>",
+                          fam.m16 ? strassen::m16_kernel_name(fam.op)
+                                  : strassen::f32_kernel_name(large),
+                          bt.wa, bt.wb, bt.wc, vec ? "vec" : "scalar", c.trans_a ? ",tA" : "",
+                          c.trans_b ? ",tB" : "");
             r.info.launch = (int32_t)bi;
             r.info.batch = batch;
             r.info.workgroups = a.tiles_m * a.tiles_n * batch;
@@ -318,6 +349,13 @@ int strassen_set_stream(void *hip_stream) {
     return 0;
 }
 
+int strassen_set_tile(int tile) {
+    if (tile != STRASSEN_TILE_AUTO && tile != STRASSEN_TILE_128 && tile != STRASSEN_TILE_256)
+        return -1;
+    g_tile.store(tile, std::memory_order_relaxed);
+    return 0;
+}
+
 int strassen_plan_info(int64_t m, int64_t n, int64_t k, int levels, strassen_dtype_t dtype,
                        strassen_mode_t mode, strassen_plan_info_t *out) {
     if (m < 0 || m >= kMaxDim) return -1;
@@ -329,8 +367,15 @@ int strassen_plan_info(int64_t m, int64_t n, int64_t k, int levels, strassen_dty
     if (mode == STRASSEN_MODE_BF16X3 && dtype != STRASSEN_F32) return -6;
     if (out == nullptr) return -7;
     try {
-        const strassen::KernelShape ks = family(dtype, mode).shape;
-        const Plan p = strassen::make_plan(m, n, k, levels, ks.vec);
+        const Family fam = family(dtype, mode);
+        const Plan p = strassen::make_plan(m, n, k, levels, fam.vec);
+        // tile of the launch with the most operand terms
+        const strassen::Batch *wide = &p.batches[0];
+        for (const strassen::Batch &b : p.batches)
+            if (b.wa + b.wb > wide->wa + wide->wb) wide = &b;
+        const bool large = !fam.m16 && use_large_f32(wide->wa, wide->wb, p.sm, p.sn,
+                                                     (int)wide->products.size());
+        const strassen::KernelShape ks = shape_of(fam, large);
         std::memset(out, 0, sizeof(*out));
         out->levels = levels;
         out->blocks_per_dim = p.d;

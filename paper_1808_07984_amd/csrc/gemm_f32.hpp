@@ -1,0 +1,361 @@
+// fp32 Strassen primitive on the gfx950 matrix cores (template; instantiated
+// per operand layout in gemm_f32_*.hip).
+//
+// One workgroup computes a MT x NT tile of one product
+//     M = (sum_t sa_t A_t)(sum_t sb_t B_t)
+// of a batch (blockIdx.z) and adds it, with signs, into the W_C output blocks
+// (eq. straprim1; Strassen's Algorithm on NVIDIA GPUs section):
+//   * A-/B-operand sums are formed in registers between the global load of
+//     every term and the store of the summed tile into LDS, so only the sum
+//     occupies LDS and nothing extra goes to HBM;
+//   * the tile product runs on v_mfma_f32_32x32x2_f32 from LDS fragments;
+//   * the fp32 accumulator is scattered to every C block once, after the k
+//     loop, so M never touches HBM;
+//   * blocks extending past the matrix read zeros and store nothing
+//     (Handling the Fringes section).
+// W_A, W_B, W_C (Register Optimization section) are template parameters, so
+// a variant with one term per operand carries no extra loads or adds.
+//
+// Operand layouts.  Each operand is staged in the direction it is contiguous
+// in memory, so global loads are 16-byte vectors and LDS stores are 16-byte:
+//   KC  (k contiguous: A as stored, or B stored transposed)  -> LDS [x][k]
+//   XC  (m/n contiguous: B as stored, or A stored transposed) -> LDS [k][x]
+// where x is the operand's m (A) or n (B) index.  Element (x, k) of a block
+// lives at off + x*ld + k (KC) or off + k*ld + x (XC).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+#include "launch.hpp"
+
+namespace strassen {
+namespace f32k {
+
+// Tile shapes.  Small: 128x128x32, 4 waves of 64x64, two workgroups per CU.
+// Large: 256x256x16, 8 waves of 128x64, one workgroup per CU; half the L2
+// traffic per flop of Small, for variants with several terms per operand.
+struct Small {
+    static constexpr int MT = 128, NT = 128, KT = 32;
+    static constexpr int WAVES_M = 2, WAVES_N = 2;
+    static constexpr int WAVES_PER_EU = 2;
+    static constexpr int GROUP = 8;
+};
+struct Large {
+    static constexpr int MT = 256, NT = 256, KT = 16;
+    static constexpr int WAVES_M = 2, WAVES_N = 4;
+    static constexpr int WAVES_PER_EU = 2;
+    static constexpr int GROUP = 4;
+};
+
+// Staging geometry of one operand tile of X x KT elements.
+template <int X, int KT, int THREADS, bool KC>
+struct Stage {
+    static constexpr int LDX = KC ? KT + 4 : X + 4;  // LDS row stride (floats)
+    static constexpr int SIZE = KC ? X * LDX : KT * LDX;
+    static constexpr int VECS = X * KT / 4 / THREADS;  // float4 per thread per term
+    static constexpr int QUADS = KC ? KT / 4 : X / 4;  // float4 per contiguous line
+    static constexpr int LINE_STEP = THREADS / QUADS;  // lines advanced per vector
+    static_assert(VECS * THREADS * 4 == X * KT, "tile split");
+    static_assert(THREADS % QUADS == 0, "whole lines per pass");
+
+    // Vector p of thread tid: element offset (x, k) of its first element.
+    __device__ static void coords(int tid, int p, int &x, int &k) {
+        const int line = tid / QUADS + p * LINE_STEP, q = (tid % QUADS) * 4;
+        if (KC) {
+            x = line;
+            k = q;
+        } else {
+            x = q;
+            k = line;
+        }
+    }
+    // LDS offset of the first element of a stored vector.
+    __device__ static int lds(int x, int k) { return KC ? x * LDX + k : k * LDX + x; }
+};
+
+// Loads the 4-vector of a block starting at (x, k) (consecutive along k for
+// KC, along x for XC), zero outside xs x ks.  Lanes whose elements are
+// outside never access memory.
+template <bool KC>
+__device__ __forceinline__ f32x4 load4_guarded(const float *__restrict__ base, int64_t ld, int x,
+                                               int k, int xs, int ks, bool vec) {
+    f32x4 v = {0.f, 0.f, 0.f, 0.f};
+    // the line index (fixed for the 4 elements) and the run index (varies)
+    const int line = KC ? x : k, run = KC ? k : x;
+    const int lines = KC ? xs : ks, runs = KC ? ks : xs;
+    if (line < lines) {
+        const float *p = base + (int64_t)line * ld + run;
+        if (vec && run + 3 < runs) {
+            v = *reinterpret_cast<const f32x4 *>(p);
+        } else {
+            if (run + 0 < runs) v.x = p[0];
+            if (run + 1 < runs) v.y = p[1];
+            if (run + 2 < runs) v.z = p[2];
+            if (run + 3 < runs) v.w = p[3];
+        }
+    }
+    return v;
+}
+
+template <class Cfg, bool A_KC, bool B_KC, int WA, int WB, int WC, bool VEC>
+__global__ __launch_bounds__(64 * Cfg::WAVES_M * Cfg::WAVES_N)
+__attribute__((amdgpu_waves_per_eu(Cfg::WAVES_PER_EU, Cfg::WAVES_PER_EU)))
+void strassen_f32_kernel(const LaunchArgs args) {
+    constexpr int MT = Cfg::MT, NT = Cfg::NT, KT = Cfg::KT;
+    constexpr int THREADS = 64 * Cfg::WAVES_M * Cfg::WAVES_N;
+    constexpr int WM = MT / Cfg::WAVES_M, WN = NT / Cfg::WAVES_N;  // wave tile
+    constexpr int BM = WM / 32, BN = WN / 32;  // 32x32 MFMA blocks per wave
+    using SA = Stage<MT, KT, THREADS, A_KC>;
+    using SB = Stage<NT, KT, THREADS, B_KC>;
+    static_assert(KT % 8 == 0, "k chunks of 8");
+
+    __shared__ __attribute__((aligned(16))) float As[2][SA::SIZE];
+    __shared__ __attribute__((aligned(16))) float Bs[2][SB::SIZE];
+
+    const ProductArg &P = args.prod[blockIdx.z];
+    const float *__restrict__ A = static_cast<const float *>(args.A);
+    const float *__restrict__ B = static_cast<const float *>(args.B);
+    const int64_t lda = args.lda, ldb = args.ldb;
+
+    int tm, tn;
+    tile_coords<Cfg::GROUP>(args.tiles_m, args.tiles_n, tm, tn);
+    const int row0 = tm * MT, col0 = tn * NT;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave % Cfg::WAVES_M, wn = wave / Cfg::WAVES_M;
+
+    // Extents of every term: x (m for A, n for B) and k.
+    int a_x, a_k, b_x, b_k;
+    min_extent(P.a, WA, a_x, a_k);   // A terms: rows = m extent, cols = k extent
+    {
+        int bk_, bx_;
+        min_extent(P.b, WB, bk_, bx_);  // B terms: rows = k extent, cols = n extent
+        b_x = bx_;
+        b_k = bk_;
+    }
+    const bool a_x_full = row0 + MT <= a_x;
+    const bool b_x_full = col0 + NT <= b_x;
+
+    f32x4 raw_a[WA][SA::VECS];
+    f32x4 raw_b[WB][SB::VECS];
+
+    // Issue the global loads of every term of the k-tile starting at k0.
+    auto issue = [&](int k0) {
+        const bool fast = VEC && a_x_full && b_x_full && (k0 + KT <= a_k) && (k0 + KT <= b_k);
+        if (fast) {
+#pragma unroll
+            for (int p = 0; p < SA::VECS; ++p) {
+                int x, k;
+                SA::coords(tid, p, x, k);
+                const int64_t e = A_KC ? (int64_t)(row0 + x) * lda + (k0 + k)
+                                       : (int64_t)(k0 + k) * lda + (row0 + x);
+#pragma unroll
+                for (int t = 0; t < WA; ++t)
+                    raw_a[t][p] = *reinterpret_cast<const f32x4 *>(A + P.a[t].off + e);
+            }
+#pragma unroll
+            for (int p = 0; p < SB::VECS; ++p) {
+                int x, k;
+                SB::coords(tid, p, x, k);
+                const int64_t e = B_KC ? (int64_t)(col0 + x) * ldb + (k0 + k)
+                                       : (int64_t)(k0 + k) * ldb + (col0 + x);
+#pragma unroll
+                for (int t = 0; t < WB; ++t)
+                    raw_b[t][p] = *reinterpret_cast<const f32x4 *>(B + P.b[t].off + e);
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < SA::VECS; ++p) {
+                int x, k;
+                SA::coords(tid, p, x, k);
+#pragma unroll
+                for (int t = 0; t < WA; ++t)
+                    raw_a[t][p] = load4_guarded<A_KC>(A + P.a[t].off, lda, row0 + x, k0 + k,
+                                                      P.a[t].rows, P.a[t].cols, VEC);
+            }
+#pragma unroll
+            for (int p = 0; p < SB::VECS; ++p) {
+                int x, k;
+                SB::coords(tid, p, x, k);
+#pragma unroll
+                for (int t = 0; t < WB; ++t)
+                    raw_b[t][p] = load4_guarded<B_KC>(B + P.b[t].off, ldb, col0 + x, k0 + k,
+                                                      P.b[t].cols, P.b[t].rows, VEC);
+            }
+        }
+    };
+
+    // Form the signed operand sums and store them into LDS buffer `buf`.
+    auto sum_store = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < SA::VECS; ++p) {
+            f32x4 s = raw_a[0][p] * P.a[0].sign;
+#pragma unroll
+            for (int t = 1; t < WA; ++t) s += raw_a[t][p] * P.a[t].sign;
+            int x, k;
+            SA::coords(tid, p, x, k);
+            *reinterpret_cast<f32x4 *>(&As[buf][SA::lds(x, k)]) = s;
+        }
+#pragma unroll
+        for (int p = 0; p < SB::VECS; ++p) {
+            f32x4 s = raw_b[0][p] * P.b[0].sign;
+#pragma unroll
+            for (int t = 1; t < WB; ++t) s += raw_b[t][p] * P.b[t].sign;
+            int x, k;
+            SB::coords(tid, p, x, k);
+            *reinterpret_cast<f32x4 *>(&Bs[buf][SB::lds(x, k)]) = s;
+        }
+    };
+
+    f32x16 acc[BM][BN];
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j) acc[i][j] = f32x16{};
+
+    // k order inside a chunk of 8: in MFMA step e, lanes 0-31 contribute
+    // k = 4*0 + e and lanes 32-63 contribute k = 4*1 + e, for A and B alike.
+    // A KC operand gives a lane its values for four steps in one 16-byte read;
+    // an XC operand is read one 4-byte value per step (32 consecutive x).
+    const int h = lane >> 5, l32 = lane & 31;
+    auto compute = [&](int buf) {
+        const float *as = &As[buf][0];
+        const float *bs = &Bs[buf][0];
+#pragma unroll
+        for (int c = 0; c < KT / 8; ++c) {
+            f32x4 af[BM], bf[BN];
+#pragma unroll
+            for (int i = 0; i < BM; ++i) {
+                const int x = wm * WM + i * 32 + l32;
+                if (A_KC)
+                    af[i] = *reinterpret_cast<const f32x4 *>(&as[SA::lds(x, c * 8 + h * 4)]);
+                else
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) af[i][e] = as[SA::lds(x, c * 8 + h * 4 + e)];
+            }
+#pragma unroll
+            for (int j = 0; j < BN; ++j) {
+                const int x = wn * WN + j * 32 + l32;
+                if (B_KC)
+                    bf[j] = *reinterpret_cast<const f32x4 *>(&bs[SB::lds(x, c * 8 + h * 4)]);
+                else
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) bf[j][e] = bs[SB::lds(x, c * 8 + h * 4 + e)];
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int i = 0; i < BM; ++i)
+#pragma unroll
+                    for (int j = 0; j < BN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i][e], bf[j][e],
+                                                                         acc[i][j], 0, 0, 0);
+        }
+    };
+
+    const int nk = (args.sk + KT - 1) / KT;
+    issue(0);
+    sum_store(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        const bool more = kt + 1 < nk;
+        if (more) issue((kt + 1) * KT);
+        compute(cur);
+        if (more) sum_store(cur ^ 1);
+        __syncthreads();
+    }
+
+    // Epilogue: C_o += sign_o * alpha * M for every output block; the first
+    // update of a block in launch order applies beta instead of reading C
+    // twice.  32x32 accumulator layout: lane l, register r holds row
+    // 8*(r/4) + 4*(l/32) + r%4, column l%32.  Each accumulator element is
+    // scattered to all outputs before the next one, so only one element
+    // offset is live at a time.
+    float *__restrict__ C = args.C;
+    const int64_t ldc = args.ldc;
+    const float alpha = args.alpha, beta = args.beta;
+    float g[WC];
+    int64_t coff[WC];
+    int crows[WC], ccols[WC], cfirst[WC];
+#pragma unroll
+    for (int o = 0; o < WC; ++o) {
+        g[o] = P.c[o].sign * alpha;
+        coff[o] = P.c[o].off;
+        crows[o] = P.c[o].rows;
+        ccols[o] = P.c[o].cols;
+        cfirst[o] = P.c[o].first;
+    }
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+            const int cj = col0 + wn * WN + j * 32 + l32;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int ci = row0 + wm * WM + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+                const int64_t e = (int64_t)ci * ldc + cj;
+                const float m = acc[i][j][r];
+#pragma unroll
+                for (int o = 0; o < WC; ++o) {
+                    if (ci < crows[o] && cj < ccols[o]) {
+                        float *pc = C + coff[o] + e;
+                        const float v = g[o] * m;
+                        if (cfirst[o])
+                            *pc = (beta == 0.f) ? v : beta * *pc + v;
+                        else
+                            *pc += v;
+                    }
+                }
+            }
+            // keep the scheduler from hoisting the next block's C traffic
+            // above this one (bounds the live registers of the epilogue)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+}
+
+template <class Cfg, bool A_KC, bool B_KC, int WA, int WB, int WC>
+hipError_t launch_variant(const LaunchArgs &a, int batch, bool vec, hipStream_t s) {
+    const dim3 grid(a.tiles_m * a.tiles_n, 1, batch);
+    const dim3 block(64 * Cfg::WAVES_M * Cfg::WAVES_N);
+    if (vec)
+        hipLaunchKernelGGL((strassen_f32_kernel<Cfg, A_KC, B_KC, WA, WB, WC, true>), grid, block, 0,
+                           s, a);
+    else
+        hipLaunchKernelGGL((strassen_f32_kernel<Cfg, A_KC, B_KC, WA, WB, WC, false>), grid, block,
+                           0, s, a);
+    return hipGetLastError();
+}
+
+template <class Cfg, bool A_KC, bool B_KC>
+hipError_t dispatch(int wa, int wb, int wc, const LaunchArgs &a, int batch, bool vec,
+                    hipStream_t s) {
+#define STRASSEN_CASE(X, Y, Z)        \
+    if (wa == X && wb == Y && wc == Z) \
+        return launch_variant<Cfg, A_KC, B_KC, X, Y, Z>(a, batch, vec, s);
+    // plain GEMM and the one-level variants
+    STRASSEN_CASE(1, 1, 1)
+    STRASSEN_CASE(2, 2, 2)
+    STRASSEN_CASE(2, 2, 1)
+    STRASSEN_CASE(1, 2, 2)
+    STRASSEN_CASE(2, 1, 2)
+    // two-level variants
+    STRASSEN_CASE(4, 4, 4)
+    STRASSEN_CASE(1, 4, 4)
+    STRASSEN_CASE(2, 4, 4)
+    STRASSEN_CASE(4, 1, 4)
+    STRASSEN_CASE(4, 2, 4)
+    STRASSEN_CASE(4, 4, 1)
+    STRASSEN_CASE(4, 4, 2)
+    STRASSEN_CASE(2, 2, 4)
+    STRASSEN_CASE(2, 4, 2)
+    STRASSEN_CASE(4, 2, 2)
+#undef STRASSEN_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace f32k
+}  // namespace strassen

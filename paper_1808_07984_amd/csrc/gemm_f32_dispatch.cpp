@@ -1,0 +1,29 @@
+// Host-side selection among the fp32 kernel instantiations.
+#include "launch.hpp"
+
+namespace strassen {
+
+KernelShape f32_tile_shape(bool large) {
+    return large ? KernelShape{256, 256, 16, 4} : KernelShape{128, 128, 32, 4};
+}
+
+hipError_t launch_f32(bool trans_a, bool trans_b, bool large, int wa, int wb, int wc,
+                      const LaunchArgs &a, int batch, bool vec, hipStream_t s) {
+    if (!trans_a && !trans_b)
+        return large ? launch_f32_nn_l(wa, wb, wc, a, batch, vec, s)
+                     : launch_f32_nn_s(wa, wb, wc, a, batch, vec, s);
+    if (!trans_a && trans_b)
+        return large ? launch_f32_nt_l(wa, wb, wc, a, batch, vec, s)
+                     : launch_f32_nt_s(wa, wb, wc, a, batch, vec, s);
+    if (trans_a && !trans_b)
+        return large ? launch_f32_tn_l(wa, wb, wc, a, batch, vec, s)
+                     : launch_f32_tn_s(wa, wb, wc, a, batch, vec, s);
+    return large ? launch_f32_tt_l(wa, wb, wc, a, batch, vec, s)
+                 : launch_f32_tt_s(wa, wb, wc, a, batch, vec, s);
+}
+
+const char *f32_kernel_name(bool large) {
+    return large ? "strassen_f32_kernel<256x256>" : "strassen_f32_kernel<128x128>";
+}
+
+}  // namespace strassen

@@ -298,34 +298,46 @@ void strassen_m16_kernel(const LaunchArgs args) {
         __syncthreads();
     }
 
-    // Epilogue: identical to the fp32 kernel (same 32x32 accumulator layout).
+    // Epilogue: as in the fp32 kernel (same 32x32 accumulator layout); each
+    // accumulator element is scattered to all outputs before the next one.
     float *__restrict__ C = args.C;
     const int64_t ldc = args.ldc;
     const float alpha = args.alpha, beta = args.beta;
+    float g[WC];
+    int64_t coff[WC];
+    int crows[WC], ccols[WC], cfirst[WC];
 #pragma unroll
     for (int o = 0; o < WC; ++o) {
-        const TermArg co = P.c[o];
-        const float g = co.sign * alpha;
-        float *cb = C + co.off;
+        g[o] = P.c[o].sign * alpha;
+        coff[o] = P.c[o].off;
+        crows[o] = P.c[o].rows;
+        ccols[o] = P.c[o].cols;
+        cfirst[o] = P.c[o].first;
+    }
 #pragma unroll
-        for (int i = 0; i < T::BM; ++i)
+    for (int i = 0; i < T::BM; ++i)
 #pragma unroll
-            for (int j = 0; j < T::BN; ++j) {
-                const int cj = col0 + wn * T::WN + j * 32 + l32;
+        for (int j = 0; j < T::BN; ++j) {
+            const int cj = col0 + wn * T::WN + j * 32 + l32;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int ci = row0 + wm * T::WM + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-                    if (ci < co.rows && cj < co.cols) {
-                        float *pc = cb + (int64_t)ci * ldc + cj;
-                        const float v = g * acc[i][j][r];
-                        if (co.first)
+            for (int r = 0; r < 16; ++r) {
+                const int ci = row0 + wm * T::WM + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+                const int64_t e = (int64_t)ci * ldc + cj;
+                const float m = acc[i][j][r];
+#pragma unroll
+                for (int o = 0; o < WC; ++o) {
+                    if (ci < crows[o] && cj < ccols[o]) {
+                        float *pc = C + coff[o] + e;
+                        const float v = g[o] * m;
+                        if (cfirst[o])
                             *pc = (beta == 0.f) ? v : beta * *pc + v;
                         else
                             *pc += v;
                     }
                 }
             }
-    }
+            __builtin_amdgcn_sched_barrier(0);
+        }
 }
 
 template <class Ops, int WA, int WB, int WC>

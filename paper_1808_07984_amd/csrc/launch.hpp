@@ -13,11 +13,24 @@ struct KernelShape {
 };
 
 // fp32 operands, fp32 MFMA.  Launches one batch of `batch` products of
-// variant (wa, wb, wc); vec = 16-byte loads are aligned (see api.cpp).
-KernelShape f32_tile_shape();
-hipError_t launch_f32(int wa, int wb, int wc, const LaunchArgs &a, int batch, bool vec,
-                      hipStream_t s);
-const char *f32_kernel_name();
+// variant (wa, wb, wc); vec = 16-byte loads are aligned (see api.cpp);
+// trans_x = operand stored transposed; large = 256x256 tile (else 128x128).
+KernelShape f32_tile_shape(bool large);
+hipError_t launch_f32(bool trans_a, bool trans_b, bool large, int wa, int wb, int wc,
+                      const LaunchArgs &a, int batch, bool vec, hipStream_t s);
+const char *f32_kernel_name(bool large);
+#define STRASSEN_F32_DECL(name)                                                         \
+    hipError_t name(int wa, int wb, int wc, const LaunchArgs &a, int batch, bool vec, \
+                    hipStream_t s);
+STRASSEN_F32_DECL(launch_f32_nn_s)
+STRASSEN_F32_DECL(launch_f32_nn_l)
+STRASSEN_F32_DECL(launch_f32_nt_s)
+STRASSEN_F32_DECL(launch_f32_nt_l)
+STRASSEN_F32_DECL(launch_f32_tn_s)
+STRASSEN_F32_DECL(launch_f32_tn_l)
+STRASSEN_F32_DECL(launch_f32_tt_s)
+STRASSEN_F32_DECL(launch_f32_tt_l)
+#undef STRASSEN_F32_DECL
 
 // 16-bit MFMA path: bf16 or fp16 operands, or fp32 operands split into
 // bf16 hi/lo pairs (compensated product hi*hi + hi*lo + lo*hi).

@@ -91,7 +91,7 @@ std::vector<Product> scheme(int levels) {
     return cur;
 }
 
-Plan make_plan(int64_t m, int64_t n, int64_t k, int levels, int vec) {
+Plan make_plan(int64_t m, int64_t n, int64_t k, int levels, int vec, bool round_m) {
     Plan p;
     p.levels = levels;
     p.d = 1 << levels;
@@ -104,6 +104,7 @@ Plan make_plan(int64_t m, int64_t n, int64_t k, int levels, int vec) {
     if (levels > 0 && vec > 1) {
         p.sn = round_up(p.sn, vec);
         p.sk = round_up(p.sk, vec);
+        if (round_m) p.sm = round_up(p.sm, vec);
     }
     const std::vector<Product> all = scheme(levels);
 

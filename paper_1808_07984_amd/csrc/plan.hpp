@@ -46,8 +46,9 @@ struct Plan {
 std::vector<Product> scheme(int levels);
 
 // Full plan.  `vec` is the vector width in elements that block offsets along
-// n and k are rounded to when levels >= 1 (so vector loads stay aligned).
-Plan make_plan(int64_t m, int64_t n, int64_t k, int levels, int vec);
+// n and k (and m when round_m is set: A stored transposed) are rounded to when
+// levels >= 1, so vector loads stay aligned.
+Plan make_plan(int64_t m, int64_t n, int64_t k, int levels, int vec, bool round_m = false);
 
 // Rows (or columns) of block index `b` (0 <= b < d) that lie inside a
 // dimension of size `dim` when blocks have extent `s`:  clamp(dim - b*s, 0, s).

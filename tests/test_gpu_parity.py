@@ -214,3 +214,85 @@ def test_full_size_awkward_integer_exact():
     intermediate well below 2^23)."""
     _sampled(15001, 17003, 9007, 2, 1.5, 0.5, lda=9024, ldb=17024, ldc=17024,
              kind="integers", exact=True)
+
+
+@pytest.fixture
+def tile_mode(request):
+    """Forces the fp32 tile shape for one test, then restores automatic."""
+    assert sg.strassen_set_tile(request.param) == 0
+    yield request.param
+    sg.strassen_set_tile(sg.STRASSEN_TILE_AUTO)
+
+
+TILES = [sg.STRASSEN_TILE_128, sg.STRASSEN_TILE_256]
+
+
+@pytest.mark.parametrize("tile_mode", TILES, indirect=True)
+@pytest.mark.parametrize("levels", [0, 1, 2])
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (3, 5, 7), (65, 67, 63), (301, 257, 190),
+                                   (520, 700, 333)])
+def test_integer_exact_each_tile(tile_mode, m, n, k, levels):
+    prob = make_problem(m, n, k, kind="integers", c_kind="integers")
+    dev = _run(prob, levels, 1.0, 1.0)
+    want = oracle.gemm_f64(prob["A"], prob["B"], prob["C"], 1.0, 1.0)
+    assert np.array_equal(dev["C"].cpu().double().numpy(), want)
+
+
+def _stored(x, trans, pad, fill=float("nan")):
+    """Device storage of operand x (as used in the product) -- transposed when
+    trans -- with `pad` extra NaN columns; returns the view passed to gemm."""
+    s = x.t().contiguous() if trans else x.contiguous()
+    st, view = inputs.padded(s, s.shape[1] + pad, fill=fill)
+    return st.cuda()[:, : s.shape[1]]
+
+
+@pytest.mark.parametrize("tile_mode", TILES, indirect=True)
+@pytest.mark.parametrize("ta,tb", [(0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("levels", [0, 1, 2])
+@pytest.mark.parametrize("aligned", [False, True])
+def test_transposed_integer_exact(tile_mode, ta, tb, levels, aligned):
+    """op(X) = X^T read from the stored transpose (ld padded with NaN, either
+    to a multiple of 4 -- 16-byte loads -- or not): exact against the oracle
+    on op(A), op(B)."""
+    m, n, k = 301, 257, 190
+    prob = make_problem(m, n, k, kind="integers", c_kind="integers")
+
+    def pad(cols, extra):
+        return (-cols) % 4 + 4 if aligned else extra
+
+    A = _stored(prob["A"], ta, pad(m if ta else k, 5))
+    B = _stored(prob["B"], tb, pad(k if tb else n, 3))
+    C = prob["C"].cuda()
+    print("case trans_a=%d trans_b=%d L=%d tile=%d" % (ta, tb, levels, tile_mode), flush=True)
+    sg.gemm(A, B, C, 1.5, 0.5, levels=levels, trans_a=bool(ta), trans_b=bool(tb))
+    torch.cuda.synchronize()
+    want = oracle.gemm_f64(prob["A"], prob["B"], prob["C"], 1.5, 0.5)
+    assert np.array_equal(C.cpu().double().numpy(), want)
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("levels", [1, 2])
+def test_transposed_float_within_tolerance(ta, tb, levels):
+    m, n, k = 1000, 700, 1100
+    prob = make_problem(m, n, k, kind="uniform", c_kind="uniform")
+    A = _stored(prob["A"], ta, 0)
+    B = _stored(prob["B"], tb, 0)
+    C = prob["C"].cuda()
+    sg.gemm(A, B, C, 1.0, 1.0, levels=levels, trans_a=bool(ta), trans_b=bool(tb))
+    torch.cuda.synchronize()
+    want = oracle.gemm_f64(prob["A"], prob["B"], prob["C"], 1.0, 1.0)
+    en = e_norm(C.cpu().double().numpy(), want, prob["A"], prob["B"], prob["C"], k, 1.0, 1.0,
+                EPS["f32"])
+    print("e_norm=%.4f (tau=%g)" % (en, tau(levels)), flush=True)
+    assert en <= tau(levels)
+
+
+@pytest.mark.parametrize("tile_mode", TILES, indirect=True)
+@pytest.mark.parametrize("levels", [1, 2])
+def test_float_each_tile(tile_mode, levels):
+    prob = make_problem(1536, 1280, 1024, kind="uniform", c_kind="uniform")
+    dev = _run(prob, levels, 1.0, 1.0)
+    want = oracle.gemm_f64(prob["A"], prob["B"], prob["C"], 1.0, 1.0)
+    en = e_norm(dev["C"].cpu().double().numpy(), want, prob["A"], prob["B"], prob["C"], 1024,
+                1.0, 1.0, EPS["f32"])
+    assert en <= tau(levels)
