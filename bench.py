@@ -44,6 +44,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-precision", action="store_true",
                    help="skip the bf16 / fp16 / bf16x3 section")
+    p.add_argument("--no-autograd", action="store_true",
+                   help="skip the forward + backward section")
     return p.parse_args()
 
 
@@ -75,6 +77,38 @@ def cpu_baseline(A, B, C, target_s):
     return {"value": flops / t / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
             "sample": "classical fp64 oracle_gemm_f64 on the first %d of %d rows of C = A*B + C "
                       "(n = k = %d), %.1f s" % (rows, A.shape[0], n, t)}
+
+
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "strassen_f32_16384_traffic.md")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None when there is no row for it or
+    the kernel sources changed since the counters were taken (the summary
+    records a sha256 of those sources)."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    m = re.search(r"kernel-source-sha256: ([0-9a-f]{64}) \(sha256 over (.*?), concatenated\)", text)
+    if not m:
+        return None
+    h = hashlib.sha256()
+    for f in m.group(2).split(", "):
+        try:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        except OSError:
+            return None
+    if h.hexdigest() != m.group(1):
+        return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 7 and cells[0] == "`%s`" % kernel:
+            return float(cells[6])
+    return None
 
 
 def time_calls(fn, steps, warmup, stream):
@@ -140,6 +174,33 @@ def precision_section(N, steps, dev, stream, log):
         out[name] = res
         del A, B, C
         torch.cuda.empty_cache()
+    return out
+
+
+def differentiation_section(steps, dev, stream, log):
+    """StrassenMatmul forward + backward (dA = dC B^T, dB = A^T dC) at the two
+    differentiation shapes, fp32, levels 1 and 2: effective TFLOP/s of the
+    three products (6mnk / t)."""
+    import torch
+    import paper_1808_07984_amd as sg
+    from paper_1808_07984_amd import inputs
+
+    out = {}
+    for (m, n, k) in ((4096, 4096, 4096), (8192, 2048, 6144)):
+        A = inputs.uniform(m, k, inputs.SEED_A).to(dev).requires_grad_(True)
+        B = inputs.uniform(k, n, inputs.SEED_B).to(dev).requires_grad_(True)
+        dC = inputs.normal(m, n, inputs.SEED_DC).to(dev)
+        for L in (0, 1, 2):
+            def step():
+                A.grad = None
+                B.grad = None
+                sg.strassen_matmul(A, B, L).backward(dC)
+            ms = time_calls(step, steps, 1, stream)
+            eff = 6.0 * m * n * k / (ms * 1e-3) / 1e12
+            out["%dx%dx%d_L%d" % (m, n, k, L)] = {"ms_per_step": round(ms, 4),
+                                                  "effective_tflops": round(eff, 2)}
+            log("autograd %dx%dx%d L%d: %.3f ms fwd+bwd  effective %.1f TFLOP/s" % (m, n, k, L, ms, eff))
+        del A, B, dC
     return out
 
 
@@ -233,7 +294,8 @@ def main():
     dom_name, (dom_ms, dom_flops, dom_n) = dom
     achieved = dom_flops / (dom_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP32_MFMA_PEAK,
-                "unit": "TFLOP/s", "frac": round(achieved / FP32_MFMA_PEAK, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_MFMA_PEAK, 4),
+                "traffic": measured_traffic(dom_name),
                 "kernel": dom_name, "launches": dom_n,
                 "avg_launch_ms": round(dom_ms / dom_n, 4),
                 "flops_per_launch": dom_flops / dom_n}
@@ -244,6 +306,10 @@ def main():
         del C0
         torch.cuda.empty_cache()
         precision = precision_section(N, max(1, min(args.steps, 5)), dev, stream, log)
+
+    autograd = None
+    if not args.no_autograd:
+        autograd = differentiation_section(max(1, min(args.steps, 5)), dev, stream, log)
 
     head = per_level["L%d" % args.levels]
     result = {
@@ -266,6 +332,10 @@ def main():
         "parity_sampled_e_norm": parity,
         "roofline": roofline,
     }
+    if autograd is not None:
+        result["differentiation"] = {"workload": "StrassenMatmul forward + backward, fp32, "
+                                                 "A,B ~ U[-1,1], dC ~ N(0,1); 6mnk flops per step",
+                                     **autograd}
     if precision is not None:
         result["precision"] = {"workload": "A,B ~ N(0,1) seeded, C := A*B (beta 0), m=n=k=%d; "
                                            "errors on 256 sampled entries vs the fp64 oracle" % N,
