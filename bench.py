@@ -281,6 +281,28 @@ def main():
         log("L%d: %.3f ms/step  effective %.1f TFLOP/s  executed %.1f TFLOP/s  (wall %.2f s)"
             % (L, ms, eff, exe, wall))
 
+    # Hybrid two-level scheme (workspace for the top-level operand sums,
+    # allocated here, outside the timed region; the library allocates nothing)
+    ws = torch.empty(sg.strassen_hybrid_workspace_size(m, n, k), dtype=torch.uint8, device=dev)
+    C.copy_(C0)
+    sg.gemm_hybrid(A, B, C, 1.0, 1.0, workspace=ws)
+    torch.cuda.synchronize()
+    got = C[torch.as_tensor(rows, device=dev), torch.as_tensor(cols, device=dev)].double().cpu().numpy()
+    en = float(np.abs(got - want).max()) / (2.0 ** -23 * scale)
+    parity["L2_hybrid"] = round(en, 4)
+    if not en <= 8.0:
+        raise SystemExit("parity failure (hybrid)")
+    ms = time_calls(lambda: sg.gemm_hybrid(A, B, C, 1.0, 1.0, workspace=ws), args.steps,
+                    args.warmup, stream)
+    info2 = sg.plan_info(m, n, k, 2)
+    per_level["L2_hybrid"] = {"ms_per_step": round(ms, 4),
+                              "effective_tflops": round(2.0 * m * n * k / (ms * 1e-3) / 1e12, 2),
+                              "executed_tflops": round(info2.executed_flops / (ms * 1e-3) / 1e12, 2),
+                              "workspace_bytes": int(ws.numel())}
+    log("L2 hybrid: %.3f ms/step  effective %.1f TFLOP/s  (sampled e_norm %.4f)"
+        % (ms, per_level["L2_hybrid"]["effective_tflops"], en))
+    del ws
+
     # Dominant kernel of the headline level: the instantiation with the most
     # device time; achieved = its executed flops / its launch time.
     by_kernel = {}

@@ -99,6 +99,34 @@ int strassen_gemm_ex(int64_t m, int64_t n, int64_t k,
                      float alpha, float beta, int levels,
                      strassen_mode_t mode, void *hip_stream);
 
+/* Hybrid two-level Strassen (Two-Level Strassen's Algorithm section, the
+ * hybrid variant): the top level forms each product's signed quadrant sums
+ * P = sum +-A_q and Q = sum +-B_q into caller-provided workspace; the fused
+ * one-level kernels then compute P*Q and scatter it, with signs, straight into
+ * the sixteen C blocks of the two-level partition, so C needs no workspace and
+ * each operand sum on the device side has at most two terms.  fp32, row-major,
+ * same semantics and degenerate cases as strassen_gemm with levels = 2.
+ * workspace: device memory of at least strassen_hybrid_workspace_size(m,n,k)
+ * bytes, 16-byte aligned, not overlapping A, B or C; owned by the caller,
+ * contents undefined after the call; it may be NULL when the product term is
+ * absent (m, n or k = 0, or alpha = 0).  Calls that overlap on one workspace
+ * race.  Enqueued on hip_stream (NULL = the null stream).
+ * Argument indices: m=1 n=2 k=3 A=4 lda=5 B=6 ldb=7 C=8 ldc=9 alpha=10
+ * beta=11 workspace=12 workspace_bytes=13; overlap of A or B with C -8. */
+int strassen_gemm_hybrid(int64_t m, int64_t n, int64_t k,
+                         const float *A, int64_t lda,
+                         const float *B, int64_t ldb,
+                         float *C, int64_t ldc,
+                         float alpha, float beta,
+                         void *workspace, int64_t workspace_bytes, void *hip_stream);
+
+/* Workspace bytes strassen_gemm_hybrid needs for this shape:
+ * 4 * ((2 sm)(2 sk) + (2 sk)(2 sn)) with sm = ceil(m/4) and sn, sk = ceil(n/4),
+ * ceil(k/4) rounded up to a multiple of 4 (about (mk + kn)/4 floats).  Returns
+ * the size, or a negative argument index (m=1 n=2 k=3).  Pure host
+ * computation. */
+int64_t strassen_hybrid_workspace_size(int64_t m, int64_t n, int64_t k);
+
 /* Sets the stream strassen_gemm uses on the calling thread (a hipStream_t;
  * NULL = the null stream).  Always returns 0. */
 int strassen_set_stream(void *hip_stream);

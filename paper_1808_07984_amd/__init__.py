@@ -29,6 +29,8 @@ from ._binding import (  # noqa: F401
     strassen_error_string,
     strassen_gemm,
     strassen_gemm_ex,
+    strassen_gemm_hybrid,
+    strassen_hybrid_workspace_size,
     strassen_plan_info,
     strassen_plan_instances,
     strassen_profile_start,
@@ -36,5 +38,5 @@ from ._binding import (  # noqa: F401
     strassen_set_stream,
     strassen_set_tile,
 )
-from .api import gemm, plan_info  # noqa: F401
+from .api import gemm, gemm_hybrid, plan_info  # noqa: F401
 from .autograd import StrassenMatmul, strassen_matmul  # noqa: F401

@@ -68,6 +68,9 @@ SIGNATURES = {
     "strassen_gemm": (_int, [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _f32, _f32, _int]),
     "strassen_gemm_ex": (_int, [_i64, _i64, _i64, _vp, _i64, _int, _int, _vp, _i64, _int, _int,
                                 _vp, _i64, _f32, _f32, _int, _int, _vp]),
+    "strassen_gemm_hybrid": (_int, [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _f32, _f32,
+                                    _vp, _i64, _vp]),
+    "strassen_hybrid_workspace_size": (_i64, [_i64, _i64, _i64]),
     "strassen_set_stream": (_int, [_vp]),
     "strassen_set_tile": (_int, [_int]),
     "strassen_plan_info": (_int, [_i64, _i64, _i64, _int, _int, _int,
@@ -136,6 +139,16 @@ def strassen_gemm_ex(m, n, k, A, lda, a_type, trans_a, B, ldb, b_type, trans_b, 
                      alpha, beta, levels, mode, hip_stream):
     return lib.strassen_gemm_ex(m, n, k, A, lda, a_type, trans_a, B, ldb, b_type, trans_b,
                                 C, ldc, alpha, beta, levels, mode, hip_stream)
+
+
+def strassen_gemm_hybrid(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, workspace,
+                         workspace_bytes, hip_stream):
+    return lib.strassen_gemm_hybrid(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, workspace,
+                                    workspace_bytes, hip_stream)
+
+
+def strassen_hybrid_workspace_size(m, n, k):
+    return lib.strassen_hybrid_workspace_size(m, n, k)
 
 
 def strassen_set_stream(hip_stream):

@@ -60,3 +60,33 @@ def plan_info(m, n, k, levels, dtype=torch.float32, mode="plain"):
     if rc != 0:
         raise B.StrassenError(rc, "strassen_plan_info")
     return info
+
+
+def gemm_hybrid(A, B_, C, alpha=1.0, beta=1.0, workspace=None, stream=None):
+    """Hybrid two-level Strassen: C := alpha * A @ B + beta * C in place, fp32.
+    `workspace` is a GPU tensor of at least strassen_hybrid_workspace_size
+    bytes (allocated by torch here when not given: the library itself
+    allocates nothing).  Returns C."""
+    for t, name in ((A, "A"), (B_, "B"), (C, "C")):
+        if not t.is_cuda or t.dtype != torch.float32:
+            raise TypeError("%s must be an fp32 GPU tensor" % name)
+    m, k = A.shape
+    kb, n = B_.shape
+    if kb != k or tuple(C.shape) != (m, n):
+        raise ValueError("shape mismatch")
+    need = B.strassen_hybrid_workspace_size(m, n, k)
+    if need < 0:
+        raise B.StrassenError(int(need), "strassen_hybrid_workspace_size")
+    if workspace is None:
+        workspace = torch.empty(max(need, 16), dtype=torch.uint8, device=C.device)
+    if workspace.numel() * workspace.element_size() < need:
+        raise ValueError("workspace smaller than %d bytes" % need)
+    with torch.cuda.device(C.device):
+        s = stream if stream is not None else torch.cuda.current_stream(C.device)
+        rc = B.strassen_gemm_hybrid(m, n, k, A.data_ptr(), _ld(A, "A"), B_.data_ptr(), _ld(B_, "B"),
+                                    C.data_ptr(), _ld(C, "C"), float(alpha), float(beta),
+                                    workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+                                    s.cuda_stream)
+    if rc != 0:
+        raise B.StrassenError(rc, "strassen_gemm_hybrid")
+    return C

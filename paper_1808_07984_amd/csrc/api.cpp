@@ -291,6 +291,152 @@ int run(const Call &c) {
     return 0;
 }
 
+// ---------------------------------------------------------------------------
+// Hybrid two-level scheme (Two-Level Strassen's Algorithm section): the top
+// level forms each product's signed quadrant sums P (of A) and Q (of B) in
+// caller workspace; the fused one-level kernels compute P*Q and scatter it
+// straight into the 4x4 grid of C blocks.  Geometry equals the direct two-
+// level plan's: C blocks are sm x sn, P is (2 sm) x (2 sk), Q (2 sk) x (2 sn).
+// ---------------------------------------------------------------------------
+struct HybridGeom {
+    Plan two;    // direct two-level plan: block extents sm, sn, sk
+    Plan inner;  // one-level plan of the (2sm x 2sn x 2sk) product P*Q
+    int64_t p_elems, q_elems;
+};
+
+HybridGeom hybrid_geom(int64_t m, int64_t n, int64_t k) {
+    HybridGeom g;
+    g.two = strassen::make_plan(m, n, k, 2, 4);
+    g.inner = strassen::make_plan(2 * g.two.sm, 2 * g.two.sn, 2 * g.two.sk, 1, 4);
+    g.p_elems = (2 * g.two.sm) * (2 * g.two.sk);
+    g.q_elems = (2 * g.two.sk) * (2 * g.two.sn);
+    return g;
+}
+
+int run_hybrid(const Call &c, float *ws) {
+    if (c.m == 0 || c.n == 0) return 0;
+    if (c.k == 0 || c.alpha == 0.f)
+        return (int)strassen::launch_scale(c.C, c.ldc, c.m, c.n, c.beta, c.stream);
+    const HybridGeom g = hybrid_geom(c.m, c.n, c.k);
+    const int64_t sm = g.two.sm, sn = g.two.sn, sk = g.two.sk;
+    const float *A = static_cast<const float *>(c.A);
+    const float *B = static_cast<const float *>(c.B);
+    float *P = ws;
+    float *Q = ws + g.p_elems;
+    const bool vec_a = (c.lda % 4 == 0) && ((uintptr_t)A % 16 == 0);
+    const bool vec_b = (c.ldb % 4 == 0) && ((uintptr_t)B % 16 == 0);
+    const std::vector<strassen::Product> top = strassen::scheme(1);
+    const Plan &in = g.inner;
+    bool touched[16] = {false};
+
+    LaunchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.A = P;
+    a.B = Q;
+    a.C = c.C;
+    a.lda = 2 * sk;
+    a.ldb = 2 * sn;
+    a.ldc = c.ldc;
+    a.sm = (int32_t)sm;
+    a.sn = (int32_t)sn;
+    a.sk = (int32_t)sk;
+    a.alpha = c.alpha;
+    a.beta = c.beta;
+
+    Recorder &rec = recorder();
+    for (const strassen::Product &tp : top) {
+        // P = sum of signed quadrants of A, Q = sum of signed quadrants of B
+        strassen::FormTerm ft[2];
+        for (int t = 0; t < tp.na; ++t) {
+            const int r1 = tp.a[t].block / 2, c1 = tp.a[t].block % 2;
+            ft[t].src = A + r1 * 2 * sm * c.lda + c1 * 2 * sk;
+            ft[t].rows = (int32_t)strassen::block_extent(c.m, 2 * sm, r1);
+            ft[t].cols = (int32_t)strassen::block_extent(c.k, 2 * sk, c1);
+            ft[t].sign = (float)tp.a[t].sign;
+        }
+        hipError_t err = strassen::launch_form(P, 2 * sk, 2 * sm, 2 * sk, c.lda, ft, tp.na, vec_a,
+                                               c.stream);
+        if (err != hipSuccess) return (int)err;
+        for (int t = 0; t < tp.nb; ++t) {
+            const int r1 = tp.b[t].block / 2, c1 = tp.b[t].block % 2;
+            ft[t].src = B + r1 * 2 * sk * c.ldb + c1 * 2 * sn;
+            ft[t].rows = (int32_t)strassen::block_extent(c.k, 2 * sk, r1);
+            ft[t].cols = (int32_t)strassen::block_extent(c.n, 2 * sn, c1);
+            ft[t].sign = (float)tp.b[t].sign;
+        }
+        err = strassen::launch_form(Q, 2 * sn, 2 * sk, 2 * sn, c.ldb, ft, tp.nb, vec_b, c.stream);
+        if (err != hipSuccess) return (int)err;
+
+        // P*Q by the fused one-level kernels; outputs are the top outputs'
+        // quadrants refined by the inner outputs' quadrants.
+        for (size_t bi = 0; bi < in.batches.size(); ++bi) {
+            const strassen::Batch &bt = in.batches[bi];
+            const int batch = (int)bt.products.size();
+            const int wc = bt.wc * tp.nc;
+            const bool large = use_large_f32(bt.wa, bt.wb, sm, sn, batch);
+            const strassen::KernelShape ks = strassen::f32_tile_shape(large);
+            a.tiles_m = (int32_t)((sm + ks.mt - 1) / ks.mt);
+            a.tiles_n = (int32_t)((sn + ks.nt - 1) / ks.nt);
+            for (int z = 0; z < batch; ++z) {
+                const strassen::Product &p = in.products[bt.products[z]];
+                ProductArg &pa = a.prod[z];
+                std::memset(&pa, 0, sizeof(pa));
+                for (int t = 0; t < p.na; ++t) {
+                    const int R = p.a[t].block / 2, Cc = p.a[t].block % 2;
+                    pa.a[t] = term(R * sm * (2 * sk) + Cc * sk, sm, sk, p.a[t].sign, false);
+                }
+                for (int t = 0; t < p.nb; ++t) {
+                    const int R = p.b[t].block / 2, Cc = p.b[t].block % 2;
+                    pa.b[t] = term(R * sk * (2 * sn) + Cc * sn, sk, sn, p.b[t].sign, false);
+                }
+                int o = 0;
+                for (int t1 = 0; t1 < tp.nc; ++t1)
+                    for (int t2 = 0; t2 < p.nc; ++t2, ++o) {
+                        const int q1 = tp.c[t1].block, q2 = p.c[t2].block;
+                        const int R = 2 * (q1 / 2) + q2 / 2, Cc = 2 * (q1 % 2) + q2 % 2;
+                        const bool first = !touched[R * 4 + Cc];
+                        touched[R * 4 + Cc] = true;
+                        pa.c[o] = term(R * sm * c.ldc + Cc * sn, strassen::block_extent(c.m, sm, R),
+                                       strassen::block_extent(c.n, sn, Cc),
+                                       tp.c[t1].sign * p.c[t2].sign, first);
+                    }
+            }
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            bool timed = false;
+            {
+                std::lock_guard<std::mutex> lk(rec.mu);
+                if (rec.on) {
+                    hipError_t e = rec.take(&e0);
+                    if (e == hipSuccess) e = rec.take(&e1);
+                    if (e != hipSuccess) return (int)e;
+                    timed = true;
+                }
+            }
+            if (timed && (err = hipEventRecord(e0, c.stream)) != hipSuccess) return (int)err;
+            err = strassen::launch_f32(false, false, large, bt.wa, bt.wb, wc, a, batch, true,
+                                       c.stream);
+            if (err != hipSuccess) return (int)err;
+            if (timed) {
+                if ((err = hipEventRecord(e1, c.stream)) != hipSuccess) return (int)err;
+                Record r;
+                std::memset(&r.info, 0, sizeof(r.info));
+                std::snprintf(r.info.kernel, sizeof(r.info.kernel), "%s<%d,%d,%d,vec>",
+                              strassen::f32_kernel_name(large), bt.wa, bt.wb, wc);
+                r.info.launch = (int32_t)bi;
+                r.info.batch = batch;
+                r.info.workgroups = a.tiles_m * a.tiles_n * batch;
+                r.info.flops = 2.0 * batch * (double)sm * (double)sn * (double)sk;
+                r.e0 = e0;
+                r.e1 = e1;
+                std::lock_guard<std::mutex> lk(rec.mu);
+                rec.recs.push_back(r);
+                ++rec.total;
+            }
+        }
+    }
+    return 0;
+}
+
 // Maps a strassen_gemm_ex argument index to its strassen_gemm position.
 int to_base_index(int code) {
     switch (-code) {
@@ -342,6 +488,49 @@ int strassen_gemm(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda, 
     const int r = strassen_gemm_ex(m, n, k, A, lda, STRASSEN_F32, 0, B, ldb, STRASSEN_F32, 0, C,
                                    ldc, alpha, beta, levels, STRASSEN_MODE_PLAIN, g_stream);
     return r < 0 ? to_base_index(r) : r;
+}
+
+int64_t strassen_hybrid_workspace_size(int64_t m, int64_t n, int64_t k) {
+    if (m < 0 || m >= kMaxDim) return -1;
+    if (n < 0 || n >= kMaxDim) return -2;
+    if (k < 0 || k >= kMaxDim) return -3;
+    try {
+        const HybridGeom g = hybrid_geom(m, n, k);
+        return (g.p_elems + g.q_elems) * (int64_t)sizeof(float);
+    } catch (...) {
+        return -(int64_t)hipErrorOutOfMemory;
+    }
+}
+
+int strassen_gemm_hybrid(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda,
+                         const float *B, int64_t ldb, float *C, int64_t ldc, float alpha,
+                         float beta, void *workspace, int64_t workspace_bytes, void *hip_stream) {
+    const Call c{m, n, k, A, lda, STRASSEN_F32, 0, B, ldb, STRASSEN_F32, 0, C, ldc,
+                 alpha, beta, 2, STRASSEN_MODE_PLAIN, (hipStream_t)hip_stream};
+    const int v = validate(c);
+    if (v != 0) return to_base_index(v);
+    const bool product = m > 0 && n > 0 && k > 0 && alpha != 0.f;
+    if (!product) {
+        try {
+            return run_hybrid(c, nullptr);
+        } catch (...) {
+            return (int)hipErrorOutOfMemory;
+        }
+    }
+    const int64_t need = strassen_hybrid_workspace_size(m, n, k);
+    if (need < 0) return (int)(-need);
+    if (workspace == nullptr || (uintptr_t)workspace % 16 != 0) return -12;
+    if (workspace_bytes < need) return -13;
+    const uint64_t wb = (uint64_t)need;
+    if (overlap(workspace, wb, A, span_bytes(m, k, lda, 4)) ||
+        overlap(workspace, wb, B, span_bytes(k, n, ldb, 4)) ||
+        overlap(workspace, wb, C, span_bytes(m, n, ldc, 4)))
+        return -12;
+    try {
+        return run_hybrid(c, static_cast<float *>(workspace));
+    } catch (...) {
+        return (int)hipErrorOutOfMemory;
+    }
 }
 
 int strassen_set_stream(void *hip_stream) {

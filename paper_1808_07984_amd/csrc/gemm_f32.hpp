@@ -342,6 +342,9 @@ hipError_t dispatch(int wa, int wb, int wc, const LaunchArgs &a, int batch, bool
     STRASSEN_CASE(2, 2, 1)
     STRASSEN_CASE(1, 2, 2)
     STRASSEN_CASE(2, 1, 2)
+    // hybrid two-level: one-level operands, up to four outputs
+    STRASSEN_CASE(1, 2, 4)
+    STRASSEN_CASE(2, 1, 4)
     // two-level variants
     STRASSEN_CASE(4, 4, 4)
     STRASSEN_CASE(1, 4, 4)

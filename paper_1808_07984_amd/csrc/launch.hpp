@@ -46,6 +46,17 @@ hipError_t launch_m16_f16(int wa, int wb, int wc, const LaunchArgs &a, int batch
 hipError_t launch_m16_bf16x3(int wa, int wb, int wc, const LaunchArgs &a, int batch, bool vec,
                              hipStream_t s);
 
+// Hybrid top level: out[r][c] = sum_t sign_t * src_t[r * ld_src + c], zero
+// where r >= rows_t or c >= cols_t; out is rows x cols (cols % 4 == 0) with
+// leading dimension ld_out (% 4 == 0), 16-byte aligned.  1 or 2 terms.
+struct FormTerm {
+    const float *src;
+    int32_t rows, cols;
+    float sign;
+};
+hipError_t launch_form(float *out, int64_t ld_out, int64_t rows, int64_t cols, int64_t ld_src,
+                       const FormTerm *terms, int nterms, bool vec, hipStream_t s);
+
 // C := beta * C over an m x n matrix (beta == 0 writes zeros, C not read).
 hipError_t launch_scale(float *C, int64_t ldc, int64_t m, int64_t n, float beta, hipStream_t s);
 

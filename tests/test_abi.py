@@ -116,3 +116,35 @@ def test_profile_records_nothing_without_launches():
     assert sg.strassen_profile_start() == 0
     rc, recs = sg.strassen_profile_stop()
     assert rc == 0 and recs == []
+
+
+def test_hybrid_workspace_size():
+    # (2 sm)(2 sk) + (2 sk)(2 sn) floats with sm = ceil(m/4), sn/sk = ceil(./4) rounded to 4
+    assert sg.strassen_hybrid_workspace_size(16384, 16384, 16384) == 4 * 2 * 8192 * 8192
+    m, n, k = 15001, 17003, 9007
+    sm, sn, sk = -(-m // 4), -(-(-(-n // 4)) // 4) * 4, -(-(-(-k // 4)) // 4) * 4
+    assert sg.strassen_hybrid_workspace_size(m, n, k) == 4 * (4 * sm * sk + 4 * sk * sn)
+    assert sg.strassen_hybrid_workspace_size(-1, 1, 1) == -1
+    assert sg.strassen_hybrid_workspace_size(1, 1, -1) == -3
+
+
+def test_hybrid_validation():
+    need = sg.strassen_hybrid_workspace_size(64, 64, 64)
+    A, B, C, W = 1 << 20, 1 << 22, 1 << 24, 1 << 26
+    base = [64, 64, 64, A, 64, B, 64, C, 64, 1.0, 1.0, W, need, None]
+
+    def call(**kw):
+        a = list(base)
+        idx = dict(m=0, lda=4, ldb=6, ldc=8, ws=11, wsb=12, A=3, C=7)
+        for key, v in kw.items():
+            a[idx[key]] = v
+        return sg.strassen_gemm_hybrid(*a)
+
+    assert call(m=-1) == -1
+    assert call(lda=3) == -5
+    assert call(ldc=3) == -9
+    assert call(ws=None) == -12
+    assert call(ws=W + 4) == -12          # not 16-byte aligned
+    assert call(wsb=need - 4) == -13
+    assert call(ws=C + 64) == -12         # workspace overlaps C
+    assert call(C=A + 128) == -8          # A overlaps C
