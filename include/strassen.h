@@ -87,7 +87,9 @@ int strassen_gemm(int64_t m, int64_t n, int64_t k,
 /* Extended form.  a_type and b_type must be equal.  trans_a / trans_b = 1
  * reads op(A) = A^T (A stored k x m, lda >= m) / op(B) = B^T (B stored
  * n x k, ldb >= k); the product is then op(A)*op(B), m x n, and a block of
- * op(X) is the transpose of a block of X.  hip_stream is a hipStream_t
+ * op(X) is the transpose of a block of X.  Transposed operands are available
+ * for fp32 data (modes PLAIN and BF16X3); with bf16/fp16 data they report
+ * -7 / -11.  hip_stream is a hipStream_t
  * (NULL = the null stream).
  * Argument indices: m=1 n=2 k=3 A=4 lda=5 a_type=6 trans_a=7 B=8 ldb=9
  * b_type=10 trans_b=11 C=12 ldc=13 alpha=14 beta=15 levels=16 mode=17
@@ -131,9 +133,9 @@ int64_t strassen_hybrid_workspace_size(int64_t m, int64_t n, int64_t k);
  * NULL = the null stream).  Always returns 0. */
 int strassen_set_stream(void *hip_stream);
 
-/* Workgroup tile of the fp32 kernels.  AUTO (the default) picks 256x256 when
- * every product of a launch has at least 128 such tiles and the launch at
- * least 256, else 128x128; the others force one shape for every fp32 launch
+/* Workgroup tile of the product kernels.  AUTO (the default) picks 256x256
+ * when every product of a launch has at least 128 such tiles and the launch at
+ * least 256, else 128x128; the others force one shape for every launch
  * (tuning, tests).  Process-wide; returns 0 or -1 (bad value). */
 #define STRASSEN_TILE_AUTO 0
 #define STRASSEN_TILE_128 1

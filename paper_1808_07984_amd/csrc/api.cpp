@@ -122,10 +122,9 @@ int validate(const Call &c) {
         if (overlap(c.A, span_bytes(a_rows, a_cols, c.lda, es), c.C, nc)) return -12;
         if (overlap(c.B, span_bytes(b_rows, b_cols, c.ldb, es), c.C, nc)) return -12;
     }
-    // Not built yet: transposed operands on the 16-bit path.
-    const bool m16 = c.a_type != STRASSEN_F32 || c.mode != STRASSEN_MODE_PLAIN;
-    if (m16 && c.trans_a) return -7;
-    if (m16 && c.trans_b) return -11;
+    // Transposed operands exist for fp32 data (plain and compensated) only.
+    if (c.a_type != STRASSEN_F32 && c.trans_a) return -7;
+    if (c.a_type != STRASSEN_F32 && c.trans_b) return -11;
     return 0;
 }
 
@@ -142,13 +141,11 @@ TermArg term(int64_t off, int64_t rows, int64_t cols, int sign, bool first) {
     return t;
 }
 
-// Tile choice of the fp32 kernels (strassen_set_tile): automatic, or forced
-// to 128x128 / 256x256 for tuning and testing.
+// Tile choice of the product kernels (strassen_set_tile): automatic, or
+// forced to 128x128 / 256x256 for tuning and testing.
 std::atomic<int> g_tile{STRASSEN_TILE_AUTO};
 
-bool use_large_f32(int wa, int wb, int64_t sm, int64_t sn, int batch) {
-    (void)wa;
-    (void)wb;
+bool use_large(int64_t sm, int64_t sn, int batch) {
     const int mode = g_tile.load(std::memory_order_relaxed);
     if (mode == STRASSEN_TILE_128) return false;
     if (mode == STRASSEN_TILE_256) return true;
@@ -173,11 +170,11 @@ Family family(strassen_dtype_t t, strassen_mode_t mode) {
     const Operand16 op = (t == STRASSEN_BF16) ? Operand16::kBf16
                          : (t == STRASSEN_F16) ? Operand16::kF16
                                                : Operand16::kBf16x3;
-    return Family{true, op, strassen::m16_tile_shape(op == Operand16::kBf16x3).vec};
+    return Family{true, op, strassen::m16_tile_shape(op == Operand16::kBf16x3, false).vec};
 }
 
 strassen::KernelShape shape_of(const Family &f, bool large) {
-    return f.m16 ? strassen::m16_tile_shape(f.op == strassen::Operand16::kBf16x3)
+    return f.m16 ? strassen::m16_tile_shape(f.op == strassen::Operand16::kBf16x3, large)
                  : strassen::f32_tile_shape(large);
 }
 
@@ -215,7 +212,7 @@ int run(const Call &c) {
     for (size_t bi = 0; bi < plan.batches.size(); ++bi) {
         const strassen::Batch &bt = plan.batches[bi];
         const int batch = (int)bt.products.size();
-        const bool large = !fam.m16 && use_large_f32(bt.wa, bt.wb, plan.sm, plan.sn, batch);
+        const bool large = use_large(plan.sm, plan.sn, batch);
         const strassen::KernelShape ks = shape_of(fam, large);
         a.tiles_m = (int32_t)((plan.sm + ks.mt - 1) / ks.mt);
         a.tiles_n = (int32_t)((plan.sn + ks.nt - 1) / ks.nt);
@@ -263,7 +260,8 @@ int run(const Call &c) {
             if (err != hipSuccess) return (int)err;
         }
         const hipError_t err =
-            fam.m16 ? strassen::launch_m16(fam.op, bt.wa, bt.wb, bt.wc, a, batch, vec, c.stream)
+            fam.m16 ? strassen::launch_m16(fam.op, c.trans_a != 0, c.trans_b != 0, large, bt.wa,
+                                           bt.wb, bt.wc, a, batch, vec, c.stream)
                     : strassen::launch_f32(c.trans_a != 0, c.trans_b != 0, large, bt.wa, bt.wb,
                                            bt.wc, a, batch, vec, c.stream);
         if (err != hipSuccess) return (int)err;
@@ -273,7 +271,7 @@ int run(const Call &c) {
             Record r;
             std::memset(&r.info, 0, sizeof(r.info));
             std::snprintf(r.info.kernel, sizeof(r.info.kernel), "%s<%d,%d,%d,%s%s%s>",
-                          fam.m16 ? strassen::m16_kernel_name(fam.op)
+                          fam.m16 ? strassen::m16_kernel_name(fam.op, large)
                                   : strassen::f32_kernel_name(large),
                           bt.wa, bt.wb, bt.wc, vec ? "vec" : "scalar", c.trans_a ? ",tA" : "",
                           c.trans_b ? ",tB" : "");
@@ -373,7 +371,7 @@ int run_hybrid(const Call &c, float *ws) {
             const strassen::Batch &bt = in.batches[bi];
             const int batch = (int)bt.products.size();
             const int wc = bt.wc * tp.nc;
-            const bool large = use_large_f32(bt.wa, bt.wb, sm, sn, batch);
+            const bool large = use_large(sm, sn, batch);
             const strassen::KernelShape ks = strassen::f32_tile_shape(large);
             a.tiles_m = (int32_t)((sm + ks.mt - 1) / ks.mt);
             a.tiles_n = (int32_t)((sn + ks.nt - 1) / ks.nt);
@@ -562,8 +560,7 @@ int strassen_plan_info(int64_t m, int64_t n, int64_t k, int levels, strassen_dty
         const strassen::Batch *wide = &p.batches[0];
         for (const strassen::Batch &b : p.batches)
             if (b.wa + b.wb > wide->wa + wide->wb) wide = &b;
-        const bool large = !fam.m16 && use_large_f32(wide->wa, wide->wb, p.sm, p.sn,
-                                                     (int)wide->products.size());
+        const bool large = use_large(p.sm, p.sn, (int)wide->products.size());
         const strassen::KernelShape ks = shape_of(fam, large);
         std::memset(out, 0, sizeof(*out));
         out->levels = levels;

@@ -1,6 +1,6 @@
-// Strassen primitive on the gfx950 16-bit matrix cores (template; each
-// operand type is instantiated in its own translation unit)
-// (v_mfma_f32_32x32x16_{bf16,f16}, fp32 accumulation).
+// Strassen primitive on the gfx950 16-bit matrix cores
+// (v_mfma_f32_32x32x16_{bf16,f16}, fp32 accumulation).  Template; each
+// operand type is instantiated in its own translation unit.
 //
 // Three operand modes share one template:
 //   * bf16 operands  -> signed sums in fp32, rounded once to bf16 (nearest
@@ -12,10 +12,13 @@
 //                       hi*hi + hi*lo + lo*hi.
 // The structure follows the fp32 kernel (eq. straprim1: sums formed while the
 // tiles are staged, signed scatter of the accumulator in the epilogue, zero
-// padding at block edges), with the operand layouts the 16-bit MFMA needs:
-// every lane supplies eight consecutive k of one row of A and eight
-// consecutive k of one column of B, so the B tile is transposed while it is
-// staged (B is stored k-major in HBM).
+// padding at block edges).  Every lane supplies eight consecutive k of one row
+// of A and of one column of B, so both LDS tiles are kept [x][k] (x = m for A,
+// n for B).  An operand that is k-contiguous in memory (A as stored, B stored
+// transposed) is copied straight in with vector stores ("direct"); an operand
+// that is m/n-contiguous (B as stored, A stored transposed) is transposed while
+// staged: each thread loads two consecutive k rows and stores one 4-byte word
+// (two k values) per column ("paired").
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,124 +29,133 @@
 #include "launch.hpp"
 
 namespace strassen {
-namespace {
+namespace m16k {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
-struct M16Tile {
-    static constexpr int MT = 128, NT = 128, KT = 32;
-    static constexpr int WAVES_M = 2, WAVES_N = 2;
-    static constexpr int THREADS = 256;
-    static constexpr int WM = 64, WN = 64, BM = 2, BN = 2;
-    // A tile: row-major, k contiguous, row stride 40 elements (80 bytes): the
-    // eight rows read by one 16-byte LDS cycle land in eight distinct bank
-    // groups.  B tile: transposed (column j holds its k values contiguously),
-    // column stride 36 elements (18 words): 32 consecutive columns map to 32
-    // distinct even banks, so the 8-byte fragment reads and the 4-byte staging
-    // writes are conflict free.
-    static constexpr int AS = KT + 8;
-    static constexpr int BS = KT + 4;
-    static constexpr int GROUP = 8;
+// Tile shapes.  LDS row strides are in 16-bit elements: direct tiles use
+// KT + 8 (the eight rows of one 16-byte read cycle land in distinct bank
+// groups), paired tiles KT + 4 (32 consecutive columns fall on 32 distinct
+// even banks for the 8-byte reads, and the 4-byte staging stores of one wave
+// on 64 distinct banks).
+template <int MT_, int NT_, int KT_, int WAVES_M_, int WAVES_N_, int GROUP_>
+struct Cfg {
+    static constexpr int MT = MT_, NT = NT_, KT = KT_;
+    static constexpr int WAVES_M = WAVES_M_, WAVES_N = WAVES_N_;
+    static constexpr int THREADS = 64 * WAVES_M * WAVES_N;
+    static constexpr int WM = MT / WAVES_M, WN = NT / WAVES_N;
+    static constexpr int BM = WM / 32, BN = WN / 32;
+    static constexpr int GROUP = GROUP_;
+    static_assert(KT % 16 == 0, "k steps of 16");
 };
+using Small = Cfg<128, 128, 32, 2, 2, 8>;
+using Large = Cfg<256, 256, 32, 2, 4, 4>;     // 16-bit operands
+using LargeX3 = Cfg<256, 256, 16, 2, 4, 4>;   // fp32 operands split hi/lo
 
-// Element types.  In: storage type of A and B.  Mf: MFMA operand type.
+// Operand types.
 struct Bf16Ops {
     using In = unsigned short;  // raw bf16 bits
+    using Vec = u16x8;          // one 16-byte load
+    static constexpr int NV = 8;
     static constexpr bool kX3 = false;
-    static constexpr int kInVec = 8;  // elements per 16-byte load
     __device__ static float to_f32(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
     __device__ static unsigned short from_f32(float f) {
-        const __bf16 b = (__bf16)f;
-        return __builtin_bit_cast(unsigned short, b);
+        return __builtin_bit_cast(unsigned short, (__bf16)f);
     }
 };
-
 struct F16Ops {
     using In = unsigned short;  // raw fp16 bits
+    using Vec = u16x8;
+    static constexpr int NV = 8;
     static constexpr bool kX3 = false;
-    static constexpr int kInVec = 8;
     __device__ static float to_f32(unsigned short h) {
         return (float)__builtin_bit_cast(_Float16, h);
     }
     __device__ static unsigned short from_f32(float f) {
-        const _Float16 v = (_Float16)f;
-        return __builtin_bit_cast(unsigned short, v);
+        return __builtin_bit_cast(unsigned short, (_Float16)f);
     }
 };
-
 struct X3Ops {
     using In = float;
+    using Vec = f32x4;
+    static constexpr int NV = 4;
     static constexpr bool kX3 = true;
-    static constexpr int kInVec = 4;
+    __device__ static float to_f32(float x) { return x; }
     __device__ static unsigned short from_f32(float f) {
-        const __bf16 b = (__bf16)f;
-        return __builtin_bit_cast(unsigned short, b);
+        return __builtin_bit_cast(unsigned short, (__bf16)f);
     }
-    __device__ static float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+    __device__ static float bf16_to_f32(unsigned short h) {
+        return __uint_as_float((unsigned)h << 16);
+    }
 };
 
-// Raw register image of eight consecutive elements of one operand row.
-template <class Ops> struct Raw8;
-template <> struct Raw8<Bf16Ops> { u16x8 v; };
-template <> struct Raw8<F16Ops> { u16x8 v; };
-template <> struct Raw8<X3Ops> { f32x4 v0, v1; };
+// Staging geometry of one operand (X = MT or NT rows of the [x][k] tile).
+// direct: units of one x row and NV consecutive k; paired: units of two
+// consecutive k rows and NV consecutive x.
+template <class C, class Ops, int X, bool DIRECT>
+struct Stage {
+    static constexpr int NV = Ops::NV;
+    static constexpr int LDX = DIRECT ? C::KT + 8 : C::KT + 4;
+    static constexpr int SIZE = X * LDX;
+    static constexpr int UNITS = DIRECT ? X * C::KT / NV : (C::KT / 2) * (X / NV);
+    static constexpr int VECS = UNITS / C::THREADS;  // units per thread per term
+    static constexpr int LOADS = DIRECT ? 1 : 2;     // global vectors per unit
+    static_assert(VECS * C::THREADS == UNITS, "tile split");
 
-// Loads elements (r, c..c+7) of a block; zero outside rows x cols.  fast: the
-// whole run is inside the block and 16-byte aligned (no predicates); lanes
-// whose elements are outside never access memory.
-template <class Ops>
-__device__ __forceinline__ Raw8<Ops> load8(const typename Ops::In *__restrict__ base, int64_t ld,
-                                           int r, int c, int rows, int cols, bool fast, bool vec) {
-    Raw8<Ops> out;
-    const typename Ops::In *p = base + (int64_t)r * ld + c;
-    if constexpr (Ops::kX3) {
-        out.v0 = f32x4{0.f, 0.f, 0.f, 0.f};
-        out.v1 = out.v0;
-        if (fast || (r < rows && vec && c + 7 < cols)) {
-            out.v0 = *reinterpret_cast<const f32x4 *>(p);
-            out.v1 = *reinterpret_cast<const f32x4 *>(p + 4);
-        } else if (r < rows) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (c + e < cols) out.v0[e] = p[e];
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (c + 4 + e < cols) out.v1[e] = p[4 + e];
-        }
-    } else {
-        out.v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-        if (fast || (r < rows && vec && c + 7 < cols)) {
-            out.v = *reinterpret_cast<const u16x8 *>(p);
-        } else if (r < rows) {
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                if (c + e < cols) out.v[e] = p[e];
+    // Unit p of thread tid: first (x, k) it covers.
+    __device__ static void coords(int tid, int p, int &x, int &k) {
+        const int u = tid + p * C::THREADS;
+        if (DIRECT) {
+            constexpr int PER_ROW = C::KT / NV;
+            x = u / PER_ROW;
+            k = (u % PER_ROW) * NV;
+        } else {
+            constexpr int PAIRS = C::KT / 2;
+            k = 2 * (u % PAIRS);
+            x = (u / PAIRS) * NV;
         }
     }
-    return out;
-}
+};
 
-// Element e of a raw image as fp32.
+// Loads NV consecutive elements of a block starting at (line, run), zero
+// outside lines x runs.  fast: the whole run is inside and aligned.  Lanes
+// whose elements are outside never access memory.
 template <class Ops>
-__device__ __forceinline__ float elem(const Raw8<Ops> &x, int e) {
-    if constexpr (Ops::kX3)
-        return e < 4 ? x.v0[e] : x.v1[e - 4];
-    else
-        return Ops::to_f32(x.v[e]);
+__device__ __forceinline__ typename Ops::Vec load_vec(const typename Ops::In *__restrict__ base,
+                                                      int64_t ld, int line, int run, int lines,
+                                                      int runs, bool fast, bool vec) {
+    using V = typename Ops::Vec;
+    constexpr int NV = Ops::NV;
+    V v;
+#pragma unroll
+    for (int e = 0; e < NV; ++e) v[e] = 0;
+    const typename Ops::In *p = base + (int64_t)line * ld + run;
+    if (fast || (line < lines && vec && run + NV - 1 < runs)) {
+        v = *reinterpret_cast<const V *>(p);
+    } else if (line < lines) {
+#pragma unroll
+        for (int e = 0; e < NV; ++e)
+            if (run + e < runs) v[e] = p[e];
+    }
+    return v;
 }
 
-template <class Ops, int WA, int WB, int WC, bool VEC>
-__global__ __launch_bounds__(M16Tile::THREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
-void strassen_m16_kernel(const LaunchArgs args) {
-    using T = M16Tile;
+template <class C, class Ops, bool A_KC, bool B_KC, int WA, int WB, int WC>
+__global__ __launch_bounds__(C::THREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void strassen_m16_kernel(const LaunchArgs args, const int vec) {
     using In = typename Ops::In;
+    using V = typename Ops::Vec;
+    constexpr int NV = Ops::NV;
     constexpr int NPLANES = Ops::kX3 ? 2 : 1;  // hi (and lo) tiles
-    __shared__ __attribute__((aligned(16))) unsigned short As[2][NPLANES][T::MT * T::AS];
-    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][NPLANES][T::NT * T::BS];
+    using SA = Stage<C, Ops, C::MT, A_KC>;
+    using SB = Stage<C, Ops, C::NT, B_KC>;
+    __shared__ __attribute__((aligned(16))) unsigned short As[2][NPLANES][SA::SIZE];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][NPLANES][SB::SIZE];
 
     const ProductArg &P = args.prod[blockIdx.z];
     const In *__restrict__ A = static_cast<const In *>(args.A);
@@ -151,101 +163,190 @@ void strassen_m16_kernel(const LaunchArgs args) {
     const int64_t lda = args.lda, ldb = args.ldb;
 
     int tm, tn;
-    tile_coords<T::GROUP>(args.tiles_m, args.tiles_n, tm, tn);
-    const int row0 = tm * T::MT, col0 = tn * T::NT;
+    tile_coords<C::GROUP>(args.tiles_m, args.tiles_n, tm, tn);
+    const int row0 = tm * C::MT, col0 = tn * C::NT;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wm = wave % T::WAVES_M, wn = wave / T::WAVES_M;
+    const int wm = wave % C::WAVES_M, wn = wave / C::WAVES_M;
 
-    // A staging: thread owns rows ar and ar + 64, eight k from ac.
-    const int ar = tid >> 2, ac = (tid & 3) * 8;
-    // B staging: thread owns k rows 2*bk, 2*bk+1 and columns bc..bc+7.
-    const int bk = tid & 15, bc = (tid >> 4) * 8;
+    // Extents shared by every term: x (m for A, n for B) and k.
+    int a_x, a_k, b_k, b_x;
+    min_extent(P.a, WA, a_x, a_k);  // A terms: rows = m extent, cols = k extent
+    min_extent(P.b, WB, b_k, b_x);  // B terms: rows = k extent, cols = n extent
+    const bool a_x_full = row0 + C::MT <= a_x;
+    const bool b_x_full = col0 + C::NT <= b_x;
 
-    int a_rows, a_cols, b_rows, b_cols;
-    min_extent(P.a, WA, a_rows, a_cols);
-    min_extent(P.b, WB, b_rows, b_cols);
-    const bool a_rows_full = row0 + T::MT <= a_rows;
-    const bool b_cols_full = col0 + T::NT <= b_cols;
+    V raw_a[WA][SA::VECS][SA::LOADS];
+    V raw_b[WB][SB::VECS][SB::LOADS];
 
-    Raw8<Ops> raw_a[WA][2], raw_b[WB][2];  // raw term loads of the next k-tile
-
-    // Issue the global loads of every term of the k-tile starting at k0.
-    auto stage_load = [&](int k0) {
-        const bool fast = VEC && a_rows_full && b_cols_full && (k0 + T::KT <= a_cols) &&
-                          (k0 + T::KT <= b_rows);
+    // One operand's loads.  terms[t].rows / .cols are the term's x / k
+    // extents.  KC (direct units): element (x, k) at off + x*ld + k, vectors
+    // along k; XC (paired units): element (x, k) at off + k*ld + x, vectors
+    // along x, two consecutive k rows per unit.
+    auto load_operand = [&](auto &raw, const In *base, const TermArg *terms, auto stage, auto kc,
+                            auto nterms, int64_t ld, int x0, int k0, bool fast) __attribute__((always_inline)) {
+        using S = decltype(stage);
+        constexpr bool KC = decltype(kc)::value;
+        constexpr int NT_ = decltype(nterms)::value;
 #pragma unroll
-        for (int t = 0; t < WA; ++t)
+        for (int p = 0; p < S::VECS; ++p) {
+            int x, k;
+            S::coords(tid, p, x, k);
 #pragma unroll
-            for (int p = 0; p < 2; ++p)
-                raw_a[t][p] = load8<Ops>(A + P.a[t].off, lda, row0 + ar + 64 * p, k0 + ac,
-                                         P.a[t].rows, P.a[t].cols, fast, VEC);
+            for (int t = 0; t < NT_; ++t)
 #pragma unroll
-        for (int t = 0; t < WB; ++t)
-#pragma unroll
-            for (int p = 0; p < 2; ++p)
-                raw_b[t][p] = load8<Ops>(B + P.b[t].off, ldb, k0 + 2 * bk + p, col0 + bc,
-                                         P.b[t].rows, P.b[t].cols, fast, VEC);
-    };
-
-    // Signed sums in fp32, rounded to the MFMA type (and split into hi/lo for
-    // the compensated mode), stored into LDS buffer `buf`.
-    auto stage_store = [&](int buf) {
-        float sa[2][8], sb[2][8];
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                float x = P.a[0].sign * elem<Ops>(raw_a[0][p], e);
-#pragma unroll
-                for (int t = 1; t < WA; ++t) x += P.a[t].sign * elem<Ops>(raw_a[t][p], e);
-                sa[p][e] = x;
-                float y = P.b[0].sign * elem<Ops>(raw_b[0][p], e);
-#pragma unroll
-                for (int t = 1; t < WB; ++t) y += P.b[t].sign * elem<Ops>(raw_b[t][p], e);
-                sb[p][e] = y;
-            }
-        // A: one 16-byte store per row and plane.
-#pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            u16x8 hi, lo;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                hi[e] = Ops::from_f32(sa[p][e]);
-                if constexpr (Ops::kX3) lo[e] = Ops::from_f32(sa[p][e] - Ops::bf16_to_f32(hi[e]));
-            }
-            const int off = (ar + 64 * p) * T::AS + ac;
-            *reinterpret_cast<u16x8 *>(&As[buf][0][off]) = hi;
-            if constexpr (Ops::kX3) *reinterpret_cast<u16x8 *>(&As[buf][NPLANES - 1][off]) = lo;
-        }
-        // B: transpose; one 4-byte store (two consecutive k) per column and plane.
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const unsigned short h0 = Ops::from_f32(sb[0][e]);
-            const unsigned short h1 = Ops::from_f32(sb[1][e]);
-            const int off = (bc + e) * T::BS + 2 * bk;
-            *reinterpret_cast<unsigned *>(&Bs[buf][0][off]) = (unsigned)h0 | ((unsigned)h1 << 16);
-            if constexpr (Ops::kX3) {
-                const unsigned short l0 = Ops::from_f32(sb[0][e] - Ops::bf16_to_f32(h0));
-                const unsigned short l1 = Ops::from_f32(sb[1][e] - Ops::bf16_to_f32(h1));
-                *reinterpret_cast<unsigned *>(&Bs[buf][NPLANES - 1][off]) =
-                    (unsigned)l0 | ((unsigned)l1 << 16);
-            }
+                for (int l = 0; l < S::LOADS; ++l) {
+                    // direct (KC): line x, run k; paired (XC): line k + l, run x
+                    const int line = KC ? x0 + x : k0 + k + l;
+                    const int run = KC ? k0 + k : x0 + x;
+                    const int lines = KC ? terms[t].rows : terms[t].cols;
+                    const int runs = KC ? terms[t].cols : terms[t].rows;
+                    raw[t][p][l] = load_vec<Ops>(base + terms[t].off, ld, line, run, lines, runs,
+                                                 fast, vec != 0);
+                }
         }
     };
 
-    f32x16 acc[T::BM][T::BN];
+    // Issue the global loads of every term of the k-tile starting at k0.  The
+    // extents passed for B are (rows, cols) = (k, n); for the paired layout
+    // the line is k and the run is n, for direct (B^T stored) line n, run k.
+    auto stage_load = [&](int k0) __attribute__((always_inline)) {
+        const bool fast = vec && a_x_full && b_x_full && (k0 + C::KT <= a_k) && (k0 + C::KT <= b_k);
+        // A terms carry (rows, cols) = (m, k) = (x, k) extents
+        load_operand(raw_a, A, P.a, SA{}, std::integral_constant<bool, A_KC>{},
+                     std::integral_constant<int, WA>{}, lda, row0, k0, fast);
+        // B terms carry (rows, cols) = (k, n): swap to (x, k) extents
+        TermArg bt[WB];
 #pragma unroll
-    for (int i = 0; i < T::BM; ++i)
+        for (int t = 0; t < WB; ++t) {
+            bt[t] = P.b[t];
+            bt[t].rows = P.b[t].cols;
+            bt[t].cols = P.b[t].rows;
+        }
+        load_operand(raw_b, B, bt, SB{}, std::integral_constant<bool, B_KC>{},
+                     std::integral_constant<int, WB>{}, ldb, col0, k0, fast);
+    };
+
+    // Signed sum of element e of load l of unit p over the terms, in fp32.
+    auto sum_elem = [&](auto &raw, const TermArg *terms, auto nterms, int p, int l, int e) __attribute__((always_inline)) {
+        constexpr int NT_ = decltype(nterms)::value;
+        float s = terms[0].sign * Ops::to_f32(raw[0][p][l][e]);
 #pragma unroll
-        for (int j = 0; j < T::BN; ++j) acc[i][j] = f32x16{};
+        for (int t = 1; t < NT_; ++t) s += terms[t].sign * Ops::to_f32(raw[t][p][l][e]);
+        return s;
+    };
+
+    // Signed sums rounded to the MFMA type (split into hi/lo for the
+    // compensated mode), stored into LDS buffer `buf`.
+    auto stage_store = [&](int buf) __attribute__((always_inline)) {
+        // ---- A ----
+#pragma unroll
+        for (int p = 0; p < SA::VECS; ++p) {
+            int x, k;
+            SA::coords(tid, p, x, k);
+            if constexpr (A_KC) {
+                // direct: NV consecutive k of row x
+                unsigned short hi[NV], lo[NV];
+#pragma unroll
+                for (int e = 0; e < NV; ++e) {
+                    const float s = sum_elem(raw_a, P.a, std::integral_constant<int, WA>{}, p, 0, e);
+                    hi[e] = Ops::from_f32(s);
+                    if constexpr (Ops::kX3) lo[e] = Ops::from_f32(s - Ops::bf16_to_f32(hi[e]));
+                }
+                const int off = x * SA::LDX + k;
+#pragma unroll
+                for (int q = 0; q < NPLANES; ++q) {
+                    const unsigned short *src = q == 0 ? hi : lo;
+                    if constexpr (NV == 8) {
+                        u16x8 w;
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) w[e] = src[e];
+                        *reinterpret_cast<u16x8 *>(&As[buf][q][off]) = w;
+                    } else {
+                        u16x4 w;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) w[e] = src[e];
+                        *reinterpret_cast<u16x4 *>(&As[buf][q][off]) = w;
+                    }
+                }
+            } else {
+                // paired: k rows k, k+1 of NV consecutive x
+#pragma unroll
+                for (int e = 0; e < NV; ++e) {
+                    const float s0 = sum_elem(raw_a, P.a, std::integral_constant<int, WA>{}, p, 0, e);
+                    const float s1 = sum_elem(raw_a, P.a, std::integral_constant<int, WA>{}, p, 1, e);
+                    const unsigned short h0 = Ops::from_f32(s0), h1 = Ops::from_f32(s1);
+                    const int off = (x + e) * SA::LDX + k;
+                    *reinterpret_cast<unsigned *>(&As[buf][0][off]) = (unsigned)h0 | ((unsigned)h1 << 16);
+                    if constexpr (Ops::kX3) {
+                        const unsigned short l0 = Ops::from_f32(s0 - Ops::bf16_to_f32(h0));
+                        const unsigned short l1 = Ops::from_f32(s1 - Ops::bf16_to_f32(h1));
+                        *reinterpret_cast<unsigned *>(&As[buf][NPLANES - 1][off]) =
+                            (unsigned)l0 | ((unsigned)l1 << 16);
+                    }
+                }
+            }
+        }
+        // ---- B ----
+#pragma unroll
+        for (int p = 0; p < SB::VECS; ++p) {
+            int x, k;
+            SB::coords(tid, p, x, k);
+            if constexpr (B_KC) {
+                unsigned short hi[NV], lo[NV];
+#pragma unroll
+                for (int e = 0; e < NV; ++e) {
+                    const float s = sum_elem(raw_b, P.b, std::integral_constant<int, WB>{}, p, 0, e);
+                    hi[e] = Ops::from_f32(s);
+                    if constexpr (Ops::kX3) lo[e] = Ops::from_f32(s - Ops::bf16_to_f32(hi[e]));
+                }
+                const int off = x * SB::LDX + k;
+#pragma unroll
+                for (int q = 0; q < NPLANES; ++q) {
+                    const unsigned short *src = q == 0 ? hi : lo;
+                    if constexpr (NV == 8) {
+                        u16x8 w;
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) w[e] = src[e];
+                        *reinterpret_cast<u16x8 *>(&Bs[buf][q][off]) = w;
+                    } else {
+                        u16x4 w;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) w[e] = src[e];
+                        *reinterpret_cast<u16x4 *>(&Bs[buf][q][off]) = w;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < NV; ++e) {
+                    const float s0 = sum_elem(raw_b, P.b, std::integral_constant<int, WB>{}, p, 0, e);
+                    const float s1 = sum_elem(raw_b, P.b, std::integral_constant<int, WB>{}, p, 1, e);
+                    const unsigned short h0 = Ops::from_f32(s0), h1 = Ops::from_f32(s1);
+                    const int off = (x + e) * SB::LDX + k;
+                    *reinterpret_cast<unsigned *>(&Bs[buf][0][off]) = (unsigned)h0 | ((unsigned)h1 << 16);
+                    if constexpr (Ops::kX3) {
+                        const unsigned short l0 = Ops::from_f32(s0 - Ops::bf16_to_f32(h0));
+                        const unsigned short l1 = Ops::from_f32(s1 - Ops::bf16_to_f32(h1));
+                        *reinterpret_cast<unsigned *>(&Bs[buf][NPLANES - 1][off]) =
+                            (unsigned)l0 | ((unsigned)l1 << 16);
+                    }
+                }
+            }
+        }
+    };
+
+    f32x16 acc[C::BM][C::BN];
+#pragma unroll
+    for (int i = 0; i < C::BM; ++i)
+#pragma unroll
+        for (int j = 0; j < C::BN; ++j) acc[i][j] = f32x16{};
 
     // In MFMA step s of a k-tile, lanes 0-31 supply k = 16s + 0..7 and lanes
     // 32-63 supply k = 16s + 8..15, for A and B alike.
     const int h = lane >> 5, l32 = lane & 31;
-    auto mfma = [&](const u32x4 &a, const u32x4 &b, f32x16 c) -> f32x16 {
+    auto mfma = [&](const u32x4 &a, const u32x4 &b, f32x16 c) __attribute__((always_inline)) -> f32x16 {
         if constexpr (std::is_same<Ops, F16Ops>::value)
             return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
                                                           __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
@@ -253,29 +354,35 @@ void strassen_m16_kernel(const LaunchArgs args) {
             return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
                                                            __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
     };
-    auto compute = [&](int buf) {
+    // Eight consecutive k of tile row x: one 16-byte read (direct stride is a
+    // multiple of 16 bytes) or two 8-byte reads (paired stride is a multiple
+    // of 8 bytes).
+    auto frag = [&](const unsigned short *tile, int ldx, bool direct, int x, int k) __attribute__((always_inline)) -> u32x4 {
+        const unsigned short *p = tile + x * ldx + k;
+        if (direct) return *reinterpret_cast<const u32x4 *>(p);
+        const u32x2 lo2 = *reinterpret_cast<const u32x2 *>(p);
+        const u32x2 hi2 = *reinterpret_cast<const u32x2 *>(p + 4);
+        return u32x4{lo2.x, lo2.y, hi2.x, hi2.y};
+    };
+    auto compute = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
-        for (int s = 0; s < T::KT / 16; ++s) {
-            u32x4 af[NPLANES][T::BM], bf[NPLANES][T::BN];
+        for (int s = 0; s < C::KT / 16; ++s) {
+            u32x4 af[NPLANES][C::BM], bf[NPLANES][C::BN];
 #pragma unroll
             for (int q = 0; q < NPLANES; ++q) {
 #pragma unroll
-                for (int i = 0; i < T::BM; ++i)
-                    af[q][i] = *reinterpret_cast<const u32x4 *>(
-                        &As[buf][q][(wm * T::WM + i * 32 + l32) * T::AS + 16 * s + 8 * h]);
+                for (int i = 0; i < C::BM; ++i)
+                    af[q][i] = frag(&As[buf][q][0], SA::LDX, A_KC, wm * C::WM + i * 32 + l32,
+                                    16 * s + 8 * h);
 #pragma unroll
-                for (int j = 0; j < T::BN; ++j) {
-                    const unsigned short *pb =
-                        &Bs[buf][q][(wn * T::WN + j * 32 + l32) * T::BS + 16 * s + 8 * h];
-                    const u32x2 lo2 = *reinterpret_cast<const u32x2 *>(pb);
-                    const u32x2 hi2 = *reinterpret_cast<const u32x2 *>(pb + 4);
-                    bf[q][j] = u32x4{lo2.x, lo2.y, hi2.x, hi2.y};
-                }
+                for (int j = 0; j < C::BN; ++j)
+                    bf[q][j] = frag(&Bs[buf][q][0], SB::LDX, B_KC, wn * C::WN + j * 32 + l32,
+                                    16 * s + 8 * h);
             }
 #pragma unroll
-            for (int i = 0; i < T::BM; ++i)
+            for (int i = 0; i < C::BM; ++i)
 #pragma unroll
-                for (int j = 0; j < T::BN; ++j) {
+                for (int j = 0; j < C::BN; ++j) {
                     acc[i][j] = mfma(af[0][i], bf[0][j], acc[i][j]);
                     if constexpr (Ops::kX3) {
                         acc[i][j] = mfma(af[0][i], bf[NPLANES - 1][j], acc[i][j]);
@@ -285,14 +392,14 @@ void strassen_m16_kernel(const LaunchArgs args) {
         }
     };
 
-    const int nk = (args.sk + T::KT - 1) / T::KT;
+    const int nk = (args.sk + C::KT - 1) / C::KT;
     stage_load(0);
     stage_store(0);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
         const bool more = kt + 1 < nk;
-        if (more) stage_load((kt + 1) * T::KT);
+        if (more) stage_load((kt + 1) * C::KT);
         compute(cur);
         if (more) stage_store(cur ^ 1);
         __syncthreads();
@@ -300,7 +407,7 @@ void strassen_m16_kernel(const LaunchArgs args) {
 
     // Epilogue: as in the fp32 kernel (same 32x32 accumulator layout); each
     // accumulator element is scattered to all outputs before the next one.
-    float *__restrict__ C = args.C;
+    float *__restrict__ Cm = args.C;
     const int64_t ldc = args.ldc;
     const float alpha = args.alpha, beta = args.beta;
     float g[WC];
@@ -315,19 +422,19 @@ void strassen_m16_kernel(const LaunchArgs args) {
         cfirst[o] = P.c[o].first;
     }
 #pragma unroll
-    for (int i = 0; i < T::BM; ++i)
+    for (int i = 0; i < C::BM; ++i)
 #pragma unroll
-        for (int j = 0; j < T::BN; ++j) {
-            const int cj = col0 + wn * T::WN + j * 32 + l32;
+        for (int j = 0; j < C::BN; ++j) {
+            const int cj = col0 + wn * C::WN + j * 32 + l32;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int ci = row0 + wm * T::WM + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+                const int ci = row0 + wm * C::WM + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
                 const int64_t e = (int64_t)ci * ldc + cj;
                 const float m = acc[i][j][r];
 #pragma unroll
                 for (int o = 0; o < WC; ++o) {
                     if (ci < crows[o] && cj < ccols[o]) {
-                        float *pc = C + coff[o] + e;
+                        float *pc = Cm + coff[o] + e;
                         const float v = g[o] * m;
                         if (cfirst[o])
                             *pc = (beta == 0.f) ? v : beta * *pc + v;
@@ -340,22 +447,21 @@ void strassen_m16_kernel(const LaunchArgs args) {
         }
 }
 
-template <class Ops, int WA, int WB, int WC>
+template <class C, class Ops, bool A_KC, bool B_KC, int WA, int WB, int WC>
 hipError_t launch_variant(const LaunchArgs &a, int batch, bool vec, hipStream_t s) {
     const dim3 grid(a.tiles_m * a.tiles_n, 1, batch);
-    const dim3 block(M16Tile::THREADS);
-    if (vec)
-        hipLaunchKernelGGL((strassen_m16_kernel<Ops, WA, WB, WC, true>), grid, block, 0, s, a);
-    else
-        hipLaunchKernelGGL((strassen_m16_kernel<Ops, WA, WB, WC, false>), grid, block, 0, s, a);
+    const dim3 block(C::THREADS);
+    hipLaunchKernelGGL((strassen_m16_kernel<C, Ops, A_KC, B_KC, WA, WB, WC>), grid, block, 0, s, a,
+                       vec ? 1 : 0);
     return hipGetLastError();
 }
 
-template <class Ops>
+template <class C, class Ops, bool A_KC, bool B_KC>
 hipError_t dispatch(int wa, int wb, int wc, const LaunchArgs &a, int batch, bool vec,
                     hipStream_t s) {
-#define STRASSEN_CASE(X, Y, Z) \
-    if (wa == X && wb == Y && wc == Z) return launch_variant<Ops, X, Y, Z>(a, batch, vec, s);
+#define STRASSEN_CASE(X, Y, Z)        \
+    if (wa == X && wb == Y && wc == Z) \
+        return launch_variant<C, Ops, A_KC, B_KC, X, Y, Z>(a, batch, vec, s);
     STRASSEN_CASE(1, 1, 1)
     STRASSEN_CASE(2, 2, 2)
     STRASSEN_CASE(2, 2, 1)
@@ -375,5 +481,5 @@ hipError_t dispatch(int wa, int wb, int wc, const LaunchArgs &a, int batch, bool
     return hipErrorInvalidValue;
 }
 
-}  // namespace
+}  // namespace m16k
 }  // namespace strassen

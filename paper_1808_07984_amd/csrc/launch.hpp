@@ -33,18 +33,23 @@ STRASSEN_F32_DECL(launch_f32_tt_l)
 #undef STRASSEN_F32_DECL
 
 // 16-bit MFMA path: bf16 or fp16 operands, or fp32 operands split into
-// bf16 hi/lo pairs (compensated product hi*hi + hi*lo + lo*hi).
+// bf16 hi/lo pairs (compensated product hi*hi + hi*lo + lo*hi).  Transposed
+// operands exist for the compensated mode only.  large = 256x256 tile.
 enum class Operand16 { kBf16, kF16, kBf16x3 };
-KernelShape m16_tile_shape(bool x3);
-hipError_t launch_m16(Operand16 op, int wa, int wb, int wc, const LaunchArgs &a, int batch,
-                      bool vec, hipStream_t s);
-const char *m16_kernel_name(Operand16 op);
-hipError_t launch_m16_bf16(int wa, int wb, int wc, const LaunchArgs &a, int batch, bool vec,
-                           hipStream_t s);
-hipError_t launch_m16_f16(int wa, int wb, int wc, const LaunchArgs &a, int batch, bool vec,
-                          hipStream_t s);
-hipError_t launch_m16_bf16x3(int wa, int wb, int wc, const LaunchArgs &a, int batch, bool vec,
-                             hipStream_t s);
+KernelShape m16_tile_shape(bool x3, bool large);
+hipError_t launch_m16(Operand16 op, bool trans_a, bool trans_b, bool large, int wa, int wb, int wc,
+                      const LaunchArgs &a, int batch, bool vec, hipStream_t s);
+const char *m16_kernel_name(Operand16 op, bool large);
+#define STRASSEN_M16_DECL(name)                                                              \
+    hipError_t name(bool large, int wa, int wb, int wc, const LaunchArgs &a, int batch, bool vec, \
+                    hipStream_t s);
+STRASSEN_M16_DECL(launch_m16_bf16)
+STRASSEN_M16_DECL(launch_m16_f16)
+STRASSEN_M16_DECL(launch_m16_bf16x3_nn)
+STRASSEN_M16_DECL(launch_m16_bf16x3_nt)
+STRASSEN_M16_DECL(launch_m16_bf16x3_tn)
+STRASSEN_M16_DECL(launch_m16_bf16x3_tt)
+#undef STRASSEN_M16_DECL
 
 // Hybrid top level: out[r][c] = sum_t sign_t * src_t[r * ld_src + c], zero
 // where r >= rows_t or c >= cols_t; out is rows x cols (cols % 4 == 0) with

@@ -88,3 +88,17 @@ def test_differentiation_workloads_sampled(m, n, k, levels):
     want = oracle.gemm_entries(A.t(), dC, None, r, c)
     got = dB[torch.as_tensor(r, device="cuda"), torch.as_tensor(c, device="cuda")].double().cpu().numpy()
     _check(got, want, m, 1, float(dC.abs().max()), levels)
+
+
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_backward_bf16x3_mode(levels):
+    """The compensated mode differentiates through the same transposed
+    kernels; gradients within the bf16x3 gate (eps 2^-16)."""
+    m, n, k = 64, 48, 80
+    A, B, dC, C, dA, dB = _grads(m, n, k, levels, mode="bf16x3")
+    eps = 2.0 ** -16
+    _check(C.cpu().double().numpy(), oracle.gemm_f64(A, B), k, 1, 1, levels, eps)
+    _check(dA.cpu().double().numpy(), oracle.gemm_f64(dC, B.t()), n,
+           float(dC.abs().max()), 1, levels, eps)
+    _check(dB.cpu().double().numpy(), oracle.gemm_f64(A.t(), dC), m, 1,
+           float(dC.abs().max()), levels, eps)

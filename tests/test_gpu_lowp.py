@@ -117,3 +117,53 @@ def test_lowp_full_size_sampled(kind, levels):
     print("sampled e_norm %.4f at eps=%g" % (en, GATE_EPS[kind]), flush=True)
     assert en <= tau(levels)
     assert bool(torch.isfinite(dev["C"]).all())
+
+
+@pytest.fixture
+def tile_mode(request):
+    assert sg.strassen_set_tile(request.param) == 0
+    yield request.param
+    sg.strassen_set_tile(sg.STRASSEN_TILE_AUTO)
+
+
+@pytest.mark.parametrize("tile_mode", [sg.STRASSEN_TILE_128, sg.STRASSEN_TILE_256], indirect=True)
+@pytest.mark.parametrize("kind", sorted(MODES))
+@pytest.mark.parametrize("levels", [0, 1, 2])
+@pytest.mark.parametrize("m,n,k", [(3, 5, 7), (65, 67, 63), (301, 257, 190), (520, 700, 333)])
+def test_lowp_integer_exact_each_tile(tile_mode, kind, levels, m, n, k):
+    dtype, mode = MODES[kind]
+    prob = make_problem(m, n, k, kind="integers", dtype=dtype, c_kind="integers")
+    dev = _run(prob, levels, 1.0, 1.0, mode)
+    want = oracle.gemm_f64(prob["A"], prob["B"], prob["C"], 1.0, 1.0)
+    assert np.array_equal(dev["C"].cpu().double().numpy(), want)
+
+
+@pytest.mark.parametrize("tile_mode", [sg.STRASSEN_TILE_128, sg.STRASSEN_TILE_256], indirect=True)
+@pytest.mark.parametrize("ta,tb", [(0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("levels", [0, 1, 2])
+@pytest.mark.parametrize("aligned", [False, True])
+def test_bf16x3_transposed_integer_exact(tile_mode, ta, tb, levels, aligned):
+    from paper_1808_07984_amd import inputs
+    m, n, k = 301, 257, 190
+    prob = make_problem(m, n, k, kind="integers", dtype="bf16x3", c_kind="integers")
+
+    def stored(x, trans, extra):
+        s = x.t().contiguous() if trans else x.contiguous()
+        pad = (-s.shape[1]) % 4 + 4 if aligned else extra
+        st, _ = inputs.padded(s, s.shape[1] + pad)
+        return st.cuda()[:, : s.shape[1]]
+
+    A = stored(prob["A"], ta, 5)
+    B = stored(prob["B"], tb, 3)
+    C = prob["C"].cuda()
+    sg.gemm(A, B, C, 1.5, 0.5, levels=levels, mode="bf16x3", trans_a=bool(ta), trans_b=bool(tb))
+    torch.cuda.synchronize()
+    want = oracle.gemm_f64(prob["A"], prob["B"], prob["C"], 1.5, 0.5)
+    assert np.array_equal(C.cpu().double().numpy(), want)
+
+
+def test_lowp_transposed_16bit_storage_rejected():
+    A = torch.zeros(8, 8, dtype=torch.bfloat16, device="cuda")
+    C = torch.zeros(8, 8, device="cuda")
+    with pytest.raises(sg.StrassenError):
+        sg.gemm(A, A, C, trans_a=True)
