@@ -46,6 +46,8 @@ def parse():
                    help="skip the bf16 / fp16 / bf16x3 section")
     p.add_argument("--no-autograd", action="store_true",
                    help="skip the forward + backward section")
+    p.add_argument("--no-small", action="store_true",
+                   help="skip the small-size schedule section")
     return p.parse_args()
 
 
@@ -204,6 +206,35 @@ def differentiation_section(steps, dev, stream, log):
     return out
 
 
+def small_sizes_section(steps, dev, stream, log):
+    """Small and medium squares (the regime where the paper launches products
+    concurrently with atomic updates): effective TFLOP/s of the batched and
+    the concurrent schedules at one and two levels, and of the plain GEMM."""
+    import torch
+    import paper_1808_07984_amd as sg
+    from paper_1808_07984_amd import inputs
+
+    out = {}
+    for N in (1024, 2048, 4096, 8192):
+        A = inputs.uniform(N, N, inputs.SEED_A).to(dev)
+        B = inputs.uniform(N, N, inputs.SEED_B).to(dev)
+        C = torch.zeros(N, N, device=dev)
+        row = {}
+        for name, L, sched in (("L0", 0, sg.STRASSEN_SCHEDULE_BATCHED),
+                               ("L1_batched", 1, sg.STRASSEN_SCHEDULE_BATCHED),
+                               ("L1_concurrent", 1, sg.STRASSEN_SCHEDULE_CONCURRENT),
+                               ("L2_batched", 2, sg.STRASSEN_SCHEDULE_BATCHED),
+                               ("L2_concurrent", 2, sg.STRASSEN_SCHEDULE_CONCURRENT)):
+            sg.strassen_set_schedule(sched)
+            ms = time_calls(lambda: sg.gemm(A, B, C, 1.0, 0.0, levels=L), steps, 2, stream)
+            row[name] = round(2.0 * N ** 3 / (ms * 1e-3) / 1e12, 2)
+        sg.strassen_set_schedule(sg.STRASSEN_SCHEDULE_BATCHED)
+        out["%d" % N] = row
+        log("small N=%d: %s" % (N, row))
+        del A, B, C
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -329,6 +360,10 @@ def main():
         torch.cuda.empty_cache()
         precision = precision_section(N, max(1, min(args.steps, 5)), dev, stream, log)
 
+    small = None
+    if not args.no_small:
+        small = small_sizes_section(max(3, args.steps), dev, stream, log)
+
     autograd = None
     if not args.no_autograd:
         autograd = differentiation_section(max(1, min(args.steps, 5)), dev, stream, log)
@@ -354,6 +389,9 @@ def main():
         "parity_sampled_e_norm": parity,
         "roofline": roofline,
     }
+    if small is not None:
+        result["small_sizes"] = {"workload": "fp32 C := A*B, A,B ~ U[-1,1], m=n=k=N; effective "
+                                             "TFLOP/s per schedule", **small}
     if autograd is not None:
         result["differentiation"] = {"workload": "StrassenMatmul forward + backward, fp32, "
                                                  "A,B ~ U[-1,1], dC ~ N(0,1); 6mnk flops per step",

@@ -142,6 +142,21 @@ int strassen_set_stream(void *hip_stream);
 #define STRASSEN_TILE_256 2
 int strassen_set_tile(int tile);
 
+/* Schedule of the products of one call (Task Parallelism section).
+ * BATCHED (the default): race-free batches of one variant, launched in a fixed
+ *   order; every C element is updated by plain read-modify-writes, so results
+ *   are deterministic (bitwise reproducible).
+ * CONCURRENT: C := beta*C first, then the products are launched up to eight at
+ *   a time whatever their variant, and outputs are added with fp32 atomics
+ *   (element-wise atomic update).  Fewer, fuller launches for small problems;
+ *   the order of the additions varies, so results vary in the last bits.
+ *   Applies to fp32 operands as stored (mode PLAIN, no transposes) at levels
+ *   >= 1; other calls keep the batched schedule.
+ * Process-wide; returns 0 or -1 (bad value). */
+#define STRASSEN_SCHEDULE_BATCHED 0
+#define STRASSEN_SCHEDULE_CONCURRENT 1
+int strassen_set_schedule(int schedule);
+
 /* Description of how a call of this shape is executed. */
 typedef struct {
     int32_t levels;            /* 0, 1 or 2 */

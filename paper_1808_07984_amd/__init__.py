@@ -22,6 +22,8 @@ from ._binding import (  # noqa: F401
     STRASSEN_MAX_LEVELS,
     STRASSEN_MODE_BF16X3,
     STRASSEN_MODE_PLAIN,
+    STRASSEN_SCHEDULE_BATCHED,
+    STRASSEN_SCHEDULE_CONCURRENT,
     STRASSEN_TILE_128,
     STRASSEN_TILE_256,
     STRASSEN_TILE_AUTO,
@@ -35,6 +37,7 @@ from ._binding import (  # noqa: F401
     strassen_plan_instances,
     strassen_profile_start,
     strassen_profile_stop,
+    strassen_set_schedule,
     strassen_set_stream,
     strassen_set_tile,
 )

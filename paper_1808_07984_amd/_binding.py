@@ -73,6 +73,7 @@ SIGNATURES = {
     "strassen_hybrid_workspace_size": (_i64, [_i64, _i64, _i64]),
     "strassen_set_stream": (_int, [_vp]),
     "strassen_set_tile": (_int, [_int]),
+    "strassen_set_schedule": (_int, [_int]),
     "strassen_plan_info": (_int, [_i64, _i64, _i64, _int, _int, _int,
                                   ctypes.POINTER(strassen_plan_info_t)]),
     "strassen_plan_instances": (_int, [_int, ctypes.POINTER(strassen_instance_t), _int]),
@@ -160,6 +161,13 @@ STRASSEN_TILE_AUTO, STRASSEN_TILE_128, STRASSEN_TILE_256 = 0, 1, 2
 
 def strassen_set_tile(tile):
     return lib.strassen_set_tile(tile)
+
+
+STRASSEN_SCHEDULE_BATCHED, STRASSEN_SCHEDULE_CONCURRENT = 0, 1
+
+
+def strassen_set_schedule(schedule):
+    return lib.strassen_set_schedule(schedule)
 
 
 def strassen_plan_info(m, n, k, levels, dtype=STRASSEN_F32, mode=STRASSEN_MODE_PLAIN):

@@ -30,7 +30,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I" + INCLUDE, "-I" + CSRC]
 # Packed fp32 instructions are disabled for all device code.
 DEVICE = ["-x", "hip", "--offload-arch=" + ARCH,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-ffp-contract=fast"]
+          "-ffp-contract=fast", "-munsafe-fp-atomics"]
 
 
 def _hipcc():

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstdint>
 #include <cstdio>
@@ -145,6 +146,9 @@ TermArg term(int64_t off, int64_t rows, int64_t cols, int sign, bool first) {
 // forced to 128x128 / 256x256 for tuning and testing.
 std::atomic<int> g_tile{STRASSEN_TILE_AUTO};
 
+// Schedule of the products (strassen_set_schedule).
+std::atomic<int> g_schedule{STRASSEN_SCHEDULE_BATCHED};
+
 bool use_large(int64_t sm, int64_t sn, int batch) {
     const int mode = g_tile.load(std::memory_order_relaxed);
     if (mode == STRASSEN_TILE_128) return false;
@@ -178,6 +182,99 @@ strassen::KernelShape shape_of(const Family &f, bool large) {
                  : strassen::f32_tile_shape(large);
 }
 
+// Task-parallel schedule for small problems (Task Parallelism section,
+// element-wise atomic update with batching): beta is applied to C first, then
+// the products are launched up to eight at a time regardless of variant and
+// every output is added with fp32 atomics, so one launch covers all seven
+// products at one level and seven launches the 49 at two.  The order of the
+// atomic additions is not fixed: results differ between runs in the last bits.
+int run_concurrent(const Call &c, const Plan &plan, bool vec) {
+    const int d = plan.d;
+    hipError_t err = strassen::launch_scale(c.C, c.ldc, c.m, c.n, c.beta, c.stream);
+    if (err != hipSuccess) return (int)err;
+    LaunchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.A = c.A;
+    a.B = c.B;
+    a.C = c.C;
+    a.lda = c.lda;
+    a.ldb = c.ldb;
+    a.ldc = c.ldc;
+    a.sm = (int32_t)plan.sm;
+    a.sn = (int32_t)plan.sn;
+    a.sk = (int32_t)plan.sk;
+    a.alpha = c.alpha;
+    a.beta = 1.f;
+    const int total = (int)plan.products.size();
+    const int wmax = plan.levels >= 2 ? 4 : 2;
+    Recorder &rec = recorder();
+    for (int first = 0, launch = 0; first < total; first += strassen::kMaxBatchArgs, ++launch) {
+        const int batch = std::min(strassen::kMaxBatchArgs, total - first);
+        const bool large = use_large(plan.sm, plan.sn, batch);
+        const strassen::KernelShape ks = strassen::f32_tile_shape(large);
+        a.tiles_m = (int32_t)((plan.sm + ks.mt - 1) / ks.mt);
+        a.tiles_n = (int32_t)((plan.sn + ks.nt - 1) / ks.nt);
+        for (int z = 0; z < batch; ++z) {
+            const strassen::Product &p = plan.products[first + z];
+            ProductArg &pa = a.prod[z];
+            std::memset(&pa, 0, sizeof(pa));
+            pa.na = p.na;
+            pa.nb = p.nb;
+            pa.nc = p.nc;
+            for (int t = 0; t < p.na; ++t) {
+                const int R = p.a[t].block / d, Cc = p.a[t].block % d;
+                pa.a[t] = term(R * plan.sm * c.lda + Cc * plan.sk,
+                               strassen::block_extent(c.m, plan.sm, R),
+                               strassen::block_extent(c.k, plan.sk, Cc), p.a[t].sign, false);
+            }
+            for (int t = 0; t < p.nb; ++t) {
+                const int R = p.b[t].block / d, Cc = p.b[t].block % d;
+                pa.b[t] = term(R * plan.sk * c.ldb + Cc * plan.sn,
+                               strassen::block_extent(c.k, plan.sk, R),
+                               strassen::block_extent(c.n, plan.sn, Cc), p.b[t].sign, false);
+            }
+            for (int t = 0; t < p.nc; ++t) {
+                const int R = p.c[t].block / d, Cc = p.c[t].block % d;
+                pa.c[t] = term(R * plan.sm * c.ldc + Cc * plan.sn,
+                               strassen::block_extent(c.m, plan.sm, R),
+                               strassen::block_extent(c.n, plan.sn, Cc), p.c[t].sign, false);
+            }
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        bool timed = false;
+        {
+            std::lock_guard<std::mutex> lk(rec.mu);
+            if (rec.on) {
+                hipError_t e = rec.take(&e0);
+                if (e == hipSuccess) e = rec.take(&e1);
+                if (e != hipSuccess) return (int)e;
+                timed = true;
+            }
+        }
+        if (timed && (err = hipEventRecord(e0, c.stream)) != hipSuccess) return (int)err;
+        err = large ? strassen::launch_f32_conc_l(wmax, a, batch, vec, c.stream)
+                    : strassen::launch_f32_conc_s(wmax, a, batch, vec, c.stream);
+        if (err != hipSuccess) return (int)err;
+        if (timed) {
+            if ((err = hipEventRecord(e1, c.stream)) != hipSuccess) return (int)err;
+            Record r;
+            std::memset(&r.info, 0, sizeof(r.info));
+            std::snprintf(r.info.kernel, sizeof(r.info.kernel), "%s<concurrent,%d>",
+                          strassen::f32_kernel_name(large), wmax);
+            r.info.launch = launch;
+            r.info.batch = batch;
+            r.info.workgroups = a.tiles_m * a.tiles_n * batch;
+            r.info.flops = 2.0 * batch * (double)plan.sm * (double)plan.sn * (double)plan.sk;
+            r.e0 = e0;
+            r.e1 = e1;
+            std::lock_guard<std::mutex> lk(rec.mu);
+            rec.recs.push_back(r);
+            ++rec.total;
+        }
+    }
+    return 0;
+}
+
 int run(const Call &c) {
     if (c.m == 0 || c.n == 0) return 0;
     if (c.k == 0 || c.alpha == 0.f)
@@ -208,6 +305,10 @@ int run(const Call &c) {
     const bool vec = (c.lda % fam.vec == 0) && (c.ldb % fam.vec == 0) &&
                      ((uintptr_t)c.A % 16 == 0) && ((uintptr_t)c.B % 16 == 0);
 
+    if (g_schedule.load(std::memory_order_relaxed) == STRASSEN_SCHEDULE_CONCURRENT && !fam.m16 &&
+        !c.trans_a && !c.trans_b && c.levels > 0)
+        return run_concurrent(c, plan, vec);
+
     Recorder &rec = recorder();
     for (size_t bi = 0; bi < plan.batches.size(); ++bi) {
         const strassen::Batch &bt = plan.batches[bi];
@@ -219,6 +320,9 @@ int run(const Call &c) {
         for (int z = 0; z < batch; ++z) {
             const strassen::Product &p = plan.products[bt.products[z]];
             ProductArg &pa = a.prod[z];
+            pa.na = p.na;
+            pa.nb = p.nb;
+            pa.nc = p.nc;
             // Block (R, Cc) of op(X) starts at row R, column Cc of the block
             // grid; a transposed operand stores it at column R, row Cc.
             for (int t = 0; t < p.na; ++t) {
@@ -379,6 +483,9 @@ int run_hybrid(const Call &c, float *ws) {
                 const strassen::Product &p = in.products[bt.products[z]];
                 ProductArg &pa = a.prod[z];
                 std::memset(&pa, 0, sizeof(pa));
+                pa.na = p.na;
+                pa.nb = p.nb;
+                pa.nc = p.nc * tp.nc;
                 for (int t = 0; t < p.na; ++t) {
                     const int R = p.a[t].block / 2, Cc = p.a[t].block % 2;
                     pa.a[t] = term(R * sm * (2 * sk) + Cc * sk, sm, sk, p.a[t].sign, false);
@@ -533,6 +640,13 @@ int strassen_gemm_hybrid(int64_t m, int64_t n, int64_t k, const float *A, int64_
 
 int strassen_set_stream(void *hip_stream) {
     g_stream = (hipStream_t)hip_stream;
+    return 0;
+}
+
+int strassen_set_schedule(int schedule) {
+    if (schedule != STRASSEN_SCHEDULE_BATCHED && schedule != STRASSEN_SCHEDULE_CONCURRENT)
+        return -1;
+    g_schedule.store(schedule, std::memory_order_relaxed);
     return 0;
 }
 

@@ -98,10 +98,16 @@ __device__ __forceinline__ f32x4 load4_guarded(const float *__restrict__ base, i
     return v;
 }
 
-template <class Cfg, bool A_KC, bool B_KC, int WA, int WB, int WC, bool VEC>
+// CONC: concurrent schedule -- the launch mixes products of different
+// variants (W_A, W_B, W_C are upper bounds, the product's own counts are
+// read at run time) and outputs are added with fp32 atomics, beta having been
+// applied beforehand; otherwise every term is used and the first update of a
+// C block applies beta.
+template <class Cfg, bool A_KC, bool B_KC, int WA, int WB, int WC, bool CONC>
 __global__ __launch_bounds__(64 * Cfg::WAVES_M * Cfg::WAVES_N)
 __attribute__((amdgpu_waves_per_eu(Cfg::WAVES_PER_EU, Cfg::WAVES_PER_EU)))
-void strassen_f32_kernel(const LaunchArgs args) {
+void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
+    const bool VEC = vec_flag != 0;
     constexpr int MT = Cfg::MT, NT = Cfg::NT, KT = Cfg::KT;
     constexpr int THREADS = 64 * Cfg::WAVES_M * Cfg::WAVES_N;
     constexpr int WM = MT / Cfg::WAVES_M, WN = NT / Cfg::WAVES_N;  // wave tile
@@ -127,15 +133,13 @@ void strassen_f32_kernel(const LaunchArgs args) {
     const int wave = tid >> 6;
     const int wm = wave % Cfg::WAVES_M, wn = wave / Cfg::WAVES_M;
 
-    // Extents of every term: x (m for A, n for B) and k.
+    // Terms in use (all of them unless the schedule is concurrent).
+    const int na = CONC ? P.na : WA, nb = CONC ? P.nb : WB, nc = CONC ? P.nc : WC;
+
+    // Extents shared by every term: x (m for A, n for B) and k.
     int a_x, a_k, b_x, b_k;
-    min_extent(P.a, WA, a_x, a_k);   // A terms: rows = m extent, cols = k extent
-    {
-        int bk_, bx_;
-        min_extent(P.b, WB, bk_, bx_);  // B terms: rows = k extent, cols = n extent
-        b_x = bx_;
-        b_k = bk_;
-    }
+    min_extent(P.a, na, a_x, a_k);  // A terms: rows = m extent, cols = k extent
+    min_extent(P.b, nb, b_k, b_x);  // B terms: rows = k extent, cols = n extent
     const bool a_x_full = row0 + MT <= a_x;
     const bool b_x_full = col0 + NT <= b_x;
 
@@ -154,7 +158,7 @@ void strassen_f32_kernel(const LaunchArgs args) {
                                        : (int64_t)(k0 + k) * lda + (row0 + x);
 #pragma unroll
                 for (int t = 0; t < WA; ++t)
-                    raw_a[t][p] = *reinterpret_cast<const f32x4 *>(A + P.a[t].off + e);
+                    if (t < na) raw_a[t][p] = *reinterpret_cast<const f32x4 *>(A + P.a[t].off + e);
             }
 #pragma unroll
             for (int p = 0; p < SB::VECS; ++p) {
@@ -164,7 +168,7 @@ void strassen_f32_kernel(const LaunchArgs args) {
                                        : (int64_t)(k0 + k) * ldb + (col0 + x);
 #pragma unroll
                 for (int t = 0; t < WB; ++t)
-                    raw_b[t][p] = *reinterpret_cast<const f32x4 *>(B + P.b[t].off + e);
+                    if (t < nb) raw_b[t][p] = *reinterpret_cast<const f32x4 *>(B + P.b[t].off + e);
             }
         } else {
 #pragma unroll
@@ -173,7 +177,7 @@ void strassen_f32_kernel(const LaunchArgs args) {
                 SA::coords(tid, p, x, k);
 #pragma unroll
                 for (int t = 0; t < WA; ++t)
-                    raw_a[t][p] = load4_guarded<A_KC>(A + P.a[t].off, lda, row0 + x, k0 + k,
+                    if (t < na) raw_a[t][p] = load4_guarded<A_KC>(A + P.a[t].off, lda, row0 + x, k0 + k,
                                                       P.a[t].rows, P.a[t].cols, VEC);
             }
 #pragma unroll
@@ -182,7 +186,7 @@ void strassen_f32_kernel(const LaunchArgs args) {
                 SB::coords(tid, p, x, k);
 #pragma unroll
                 for (int t = 0; t < WB; ++t)
-                    raw_b[t][p] = load4_guarded<B_KC>(B + P.b[t].off, ldb, col0 + x, k0 + k,
+                    if (t < nb) raw_b[t][p] = load4_guarded<B_KC>(B + P.b[t].off, ldb, col0 + x, k0 + k,
                                                       P.b[t].cols, P.b[t].rows, VEC);
             }
         }
@@ -194,7 +198,8 @@ void strassen_f32_kernel(const LaunchArgs args) {
         for (int p = 0; p < SA::VECS; ++p) {
             f32x4 s = raw_a[0][p] * P.a[0].sign;
 #pragma unroll
-            for (int t = 1; t < WA; ++t) s += raw_a[t][p] * P.a[t].sign;
+            for (int t = 1; t < WA; ++t)
+                if (t < na) s += raw_a[t][p] * P.a[t].sign;
             int x, k;
             SA::coords(tid, p, x, k);
             *reinterpret_cast<f32x4 *>(&As[buf][SA::lds(x, k)]) = s;
@@ -203,7 +208,8 @@ void strassen_f32_kernel(const LaunchArgs args) {
         for (int p = 0; p < SB::VECS; ++p) {
             f32x4 s = raw_b[0][p] * P.b[0].sign;
 #pragma unroll
-            for (int t = 1; t < WB; ++t) s += raw_b[t][p] * P.b[t].sign;
+            for (int t = 1; t < WB; ++t)
+                if (t < nb) s += raw_b[t][p] * P.b[t].sign;
             int x, k;
             SB::coords(tid, p, x, k);
             *reinterpret_cast<f32x4 *>(&Bs[buf][SB::lds(x, k)]) = s;
@@ -301,10 +307,12 @@ void strassen_f32_kernel(const LaunchArgs args) {
                 const float m = acc[i][j][r];
 #pragma unroll
                 for (int o = 0; o < WC; ++o) {
-                    if (ci < crows[o] && cj < ccols[o]) {
+                    if (o < nc && ci < crows[o] && cj < ccols[o]) {
                         float *pc = C + coff[o] + e;
                         const float v = g[o] * m;
-                        if (cfirst[o])
+                        if (CONC)
+                            atomicAdd(pc, v);
+                        else if (cfirst[o])
                             *pc = (beta == 0.f) ? v : beta * *pc + v;
                         else
                             *pc += v;
@@ -317,17 +325,21 @@ void strassen_f32_kernel(const LaunchArgs args) {
         }
 }
 
-template <class Cfg, bool A_KC, bool B_KC, int WA, int WB, int WC>
+template <class Cfg, bool A_KC, bool B_KC, int WA, int WB, int WC, bool CONC = false>
 hipError_t launch_variant(const LaunchArgs &a, int batch, bool vec, hipStream_t s) {
     const dim3 grid(a.tiles_m * a.tiles_n, 1, batch);
     const dim3 block(64 * Cfg::WAVES_M * Cfg::WAVES_N);
-    if (vec)
-        hipLaunchKernelGGL((strassen_f32_kernel<Cfg, A_KC, B_KC, WA, WB, WC, true>), grid, block, 0,
-                           s, a);
-    else
-        hipLaunchKernelGGL((strassen_f32_kernel<Cfg, A_KC, B_KC, WA, WB, WC, false>), grid, block,
-                           0, s, a);
+    hipLaunchKernelGGL((strassen_f32_kernel<Cfg, A_KC, B_KC, WA, WB, WC, CONC>), grid, block, 0, s,
+                       a, vec ? 1 : 0);
     return hipGetLastError();
+}
+
+// Concurrent schedule: up to two (one level) or four (two levels) terms per
+// operand and output, counts read per product.
+template <class Cfg>
+hipError_t dispatch_concurrent(int wmax, const LaunchArgs &a, int batch, bool vec, hipStream_t s) {
+    if (wmax <= 2) return launch_variant<Cfg, true, false, 2, 2, 2, true>(a, batch, vec, s);
+    return launch_variant<Cfg, true, false, 4, 4, 4, true>(a, batch, vec, s);
 }
 
 template <class Cfg, bool A_KC, bool B_KC>

@@ -8,4 +8,8 @@ hipError_t launch_f32_nn_l(int wa, int wb, int wc, const LaunchArgs &a, int batc
     return f32k::dispatch<f32k::Large, true, false>(wa, wb, wc, a, batch, vec, s);
 }
 
+hipError_t launch_f32_conc_l(int wmax, const LaunchArgs &a, int batch, bool vec, hipStream_t s) {
+    return f32k::dispatch_concurrent<f32k::Large>(wmax, a, batch, vec, s);
+}
+
 }  // namespace strassen

@@ -24,6 +24,8 @@ struct ProductArg {
     TermArg a[4];
     TermArg b[4];
     TermArg c[4];
+    int32_t na, nb, nc;  // terms in use (kernels compiled for a variant use all)
+    int32_t pad;
 };
 
 struct LaunchArgs {

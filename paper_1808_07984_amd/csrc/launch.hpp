@@ -31,6 +31,11 @@ STRASSEN_F32_DECL(launch_f32_tn_l)
 STRASSEN_F32_DECL(launch_f32_tt_s)
 STRASSEN_F32_DECL(launch_f32_tt_l)
 #undef STRASSEN_F32_DECL
+// Concurrent schedule (A and B as stored): a launch mixes products of any
+// variant with at most wmax terms per operand/output; outputs are added with
+// fp32 atomics (beta applied beforehand).
+hipError_t launch_f32_conc_s(int wmax, const LaunchArgs &a, int batch, bool vec, hipStream_t s);
+hipError_t launch_f32_conc_l(int wmax, const LaunchArgs &a, int batch, bool vec, hipStream_t s);
 
 // 16-bit MFMA path: bf16 or fp16 operands, or fp32 operands split into
 // bf16 hi/lo pairs (compensated product hi*hi + hi*lo + lo*hi).  Transposed
