@@ -146,49 +146,73 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
     f32x4 raw_a[WA][SA::VECS];
     f32x4 raw_b[WB][SB::VECS];
 
-    // Issue the global loads of every term of the k-tile starting at k0.
+    // In-bounds k-tiles: loads of k-tiles [0, nfast) need no guard.  They
+    // address each term from a uniform base pointer (scalar registers,
+    // advanced one k-tile per step) plus a per-thread 32-bit byte offset that
+    // does not change along k.
+    constexpr uint64_t kOffLimit = 1ull << 32;
+    const bool a_off32 = (uint64_t)(A_KC ? MT : KT) * (uint64_t)lda * 4u < kOffLimit;
+    const bool b_off32 = (uint64_t)(B_KC ? NT : KT) * (uint64_t)ldb * 4u < kOffLimit;
+    const int nfast = (VEC && a_x_full && b_x_full && a_off32 && b_off32)
+                          ? (a_k < b_k ? a_k : b_k) / KT : 0;
+    uint32_t a_off[SA::VECS], b_off[SB::VECS];
+#pragma unroll
+    for (int p = 0; p < SA::VECS; ++p) {
+        int x, k;
+        SA::coords(tid, p, x, k);
+        a_off[p] = 4u * (A_KC ? (uint32_t)x * (uint32_t)lda + k : (uint32_t)k * (uint32_t)lda + x);
+    }
+#pragma unroll
+    for (int p = 0; p < SB::VECS; ++p) {
+        int x, k;
+        SB::coords(tid, p, x, k);
+        b_off[p] = 4u * (B_KC ? (uint32_t)x * (uint32_t)ldb + k : (uint32_t)k * (uint32_t)ldb + x);
+    }
+    const int64_t a_step = 4 * (A_KC ? (int64_t)KT : (int64_t)KT * lda);
+    const int64_t b_step = 4 * (B_KC ? (int64_t)KT : (int64_t)KT * ldb);
+    const int64_t a_org = A_KC ? (int64_t)row0 * lda : row0;
+    const int64_t b_org = B_KC ? (int64_t)col0 * ldb : col0;
+
+    auto issue_fast = [&](int kt) {
+#pragma unroll
+        for (int t = 0; t < WA; ++t) {
+            if (t < na) {
+                const char *base = reinterpret_cast<const char *>(A + P.a[t].off + a_org) + a_step * kt;
+#pragma unroll
+                for (int p = 0; p < SA::VECS; ++p)
+                    raw_a[t][p] = *reinterpret_cast<const f32x4 *>(base + a_off[p]);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < WB; ++t) {
+            if (t < nb) {
+                const char *base = reinterpret_cast<const char *>(B + P.b[t].off + b_org) + b_step * kt;
+#pragma unroll
+                for (int p = 0; p < SB::VECS; ++p)
+                    raw_b[t][p] = *reinterpret_cast<const f32x4 *>(base + b_off[p]);
+            }
+        }
+    };
+
+    // Loads of any k-tile, each element guarded against its term's extents.
     auto issue = [&](int k0) {
-        const bool fast = VEC && a_x_full && b_x_full && (k0 + KT <= a_k) && (k0 + KT <= b_k);
-        if (fast) {
 #pragma unroll
-            for (int p = 0; p < SA::VECS; ++p) {
-                int x, k;
-                SA::coords(tid, p, x, k);
-                const int64_t e = A_KC ? (int64_t)(row0 + x) * lda + (k0 + k)
-                                       : (int64_t)(k0 + k) * lda + (row0 + x);
+        for (int p = 0; p < SA::VECS; ++p) {
+            int x, k;
+            SA::coords(tid, p, x, k);
 #pragma unroll
-                for (int t = 0; t < WA; ++t)
-                    if (t < na) raw_a[t][p] = *reinterpret_cast<const f32x4 *>(A + P.a[t].off + e);
-            }
+            for (int t = 0; t < WA; ++t)
+                if (t < na) raw_a[t][p] = load4_guarded<A_KC>(A + P.a[t].off, lda, row0 + x, k0 + k,
+                                                  P.a[t].rows, P.a[t].cols, VEC);
+        }
 #pragma unroll
-            for (int p = 0; p < SB::VECS; ++p) {
-                int x, k;
-                SB::coords(tid, p, x, k);
-                const int64_t e = B_KC ? (int64_t)(col0 + x) * ldb + (k0 + k)
-                                       : (int64_t)(k0 + k) * ldb + (col0 + x);
+        for (int p = 0; p < SB::VECS; ++p) {
+            int x, k;
+            SB::coords(tid, p, x, k);
 #pragma unroll
-                for (int t = 0; t < WB; ++t)
-                    if (t < nb) raw_b[t][p] = *reinterpret_cast<const f32x4 *>(B + P.b[t].off + e);
-            }
-        } else {
-#pragma unroll
-            for (int p = 0; p < SA::VECS; ++p) {
-                int x, k;
-                SA::coords(tid, p, x, k);
-#pragma unroll
-                for (int t = 0; t < WA; ++t)
-                    if (t < na) raw_a[t][p] = load4_guarded<A_KC>(A + P.a[t].off, lda, row0 + x, k0 + k,
-                                                      P.a[t].rows, P.a[t].cols, VEC);
-            }
-#pragma unroll
-            for (int p = 0; p < SB::VECS; ++p) {
-                int x, k;
-                SB::coords(tid, p, x, k);
-#pragma unroll
-                for (int t = 0; t < WB; ++t)
-                    if (t < nb) raw_b[t][p] = load4_guarded<B_KC>(B + P.b[t].off, ldb, col0 + x, k0 + k,
-                                                      P.b[t].cols, P.b[t].rows, VEC);
-            }
+            for (int t = 0; t < WB; ++t)
+                if (t < nb) raw_b[t][p] = load4_guarded<B_KC>(B + P.b[t].off, ldb, col0 + x, k0 + k,
+                                                  P.b[t].cols, P.b[t].rows, VEC);
         }
     };
 
@@ -263,10 +287,28 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
     };
 
     const int nk = (args.sk + KT - 1) / KT;
-    issue(0);
+    if (nfast > 0)
+        issue_fast(0);
+    else
+        issue(0);
     sum_store(0);
     __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
+    int kt = 0;
+    // Steady state: the next k-tile is in bounds, no guards, no branches.
+    for (; kt + 1 < nfast; ++kt) {
+        const int cur = kt & 1;
+        issue_fast(kt + 1);
+        // Keep the loads ahead of the MFMA block and the sums behind it: left
+        // to itself the scheduler moves them next to each other and exposes
+        // the load latency.
+        __builtin_amdgcn_sched_barrier(0);
+        compute(cur);
+        __builtin_amdgcn_sched_barrier(0);
+        sum_store(cur ^ 1);
+        __syncthreads();
+    }
+    // Remaining k-tiles (fringe workgroups, a ragged last k-tile).
+    for (; kt < nk; ++kt) {
         const int cur = kt & 1;
         const bool more = kt + 1 < nk;
         if (more) issue((kt + 1) * KT);
