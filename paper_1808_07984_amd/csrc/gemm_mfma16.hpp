@@ -229,6 +229,61 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
                      std::integral_constant<int, WB>{}, ldb, col0, k0, fast);
     };
 
+    // In-bounds k-tiles [0, nfast): unguarded loads from a uniform per-term
+    // base (advanced one k-tile per step) plus a per-thread 32-bit byte
+    // offset that does not change along k.
+    constexpr uint64_t kOffLimit = 1ull << 32;
+    const bool off32 = (uint64_t)(A_KC ? C::MT : C::KT) * (uint64_t)lda * sizeof(In) < kOffLimit &&
+                       (uint64_t)(B_KC ? C::NT : C::KT) * (uint64_t)ldb * sizeof(In) < kOffLimit;
+    // (The compensated mode with four terms on both operands has no
+    // registers to spare for the offsets and keeps the guarded loop.)
+    constexpr bool kFastLoop = !(Ops::kX3 && WA + WB >= 8);
+    const int nfast = (kFastLoop && vec && a_x_full && b_x_full && off32)
+                          ? (a_k < b_k ? a_k : b_k) / C::KT : 0;
+    uint32_t a_off[SA::VECS][SA::LOADS], b_off[SB::VECS][SB::LOADS];
+    auto unit_offsets = [&](auto &off, auto stage, auto kc, int64_t ld) __attribute__((always_inline)) {
+        using S = decltype(stage);
+        constexpr bool KC = decltype(kc)::value;
+#pragma unroll
+        for (int p = 0; p < S::VECS; ++p) {
+            int x, k;
+            S::coords(tid, p, x, k);
+#pragma unroll
+            for (int l = 0; l < S::LOADS; ++l)
+                off[p][l] = (uint32_t)sizeof(In) *
+                            (KC ? (uint32_t)x * (uint32_t)ld + k : (uint32_t)(k + l) * (uint32_t)ld + x);
+        }
+    };
+    if constexpr (kFastLoop) {
+        unit_offsets(a_off, SA{}, std::integral_constant<bool, A_KC>{}, lda);
+        unit_offsets(b_off, SB{}, std::integral_constant<bool, B_KC>{}, ldb);
+    }
+    const int64_t a_org = A_KC ? (int64_t)row0 * lda : row0;
+    const int64_t b_org = B_KC ? (int64_t)col0 * ldb : col0;
+    const int64_t a_step = (int64_t)sizeof(In) * (A_KC ? (int64_t)C::KT : (int64_t)C::KT * lda);
+    const int64_t b_step = (int64_t)sizeof(In) * (B_KC ? (int64_t)C::KT : (int64_t)C::KT * ldb);
+
+    auto load_fast = [&](auto &raw, const In *base, const TermArg *terms, auto stage, auto nterms,
+                         const auto &off, int64_t org, int64_t step, int kt) __attribute__((always_inline)) {
+        using S = decltype(stage);
+        constexpr int NT_ = decltype(nterms)::value;
+#pragma unroll
+        for (int t = 0; t < NT_; ++t) {
+            const char *tb = reinterpret_cast<const char *>(base + terms[t].off + org) + step * kt;
+#pragma unroll
+            for (int p = 0; p < S::VECS; ++p)
+#pragma unroll
+                for (int l = 0; l < S::LOADS; ++l)
+                    raw[t][p][l] = *reinterpret_cast<const V *>(tb + off[p][l]);
+        }
+    };
+    auto stage_load_fast = [&](int kt) __attribute__((always_inline)) {
+        if constexpr (kFastLoop) {
+            load_fast(raw_a, A, P.a, SA{}, std::integral_constant<int, WA>{}, a_off, a_org, a_step, kt);
+            load_fast(raw_b, B, P.b, SB{}, std::integral_constant<int, WB>{}, b_off, b_org, b_step, kt);
+        }
+    };
+
     // Signed sum of element e of load l of unit p over the terms, in fp32.
     auto sum_elem = [&](auto &raw, const TermArg *terms, auto nterms, int p, int l, int e) __attribute__((always_inline)) {
         constexpr int NT_ = decltype(nterms)::value;
@@ -393,10 +448,28 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
     };
 
     const int nk = (args.sk + C::KT - 1) / C::KT;
-    stage_load(0);
+    if (nfast > 0)
+        stage_load_fast(0);
+    else
+        stage_load(0);
     stage_store(0);
     __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
+    int kt = 0;
+    // Steady state: the next k-tile is in bounds.  The scheduling barriers
+    // keep its loads ahead of the MFMA block and the sums behind it, so the
+    // load latency is covered by a whole k-tile of MFMAs.
+    if constexpr (kFastLoop)
+    for (; kt + 1 < nfast; ++kt) {
+        const int cur = kt & 1;
+        stage_load_fast(kt + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(cur);
+        __builtin_amdgcn_sched_barrier(0);
+        stage_store(cur ^ 1);
+        __syncthreads();
+    }
+    // Remaining k-tiles (fringe workgroups, a ragged last k-tile).
+    for (; kt < nk; ++kt) {
         const int cur = kt & 1;
         const bool more = kt + 1 < nk;
         if (more) stage_load((kt + 1) * C::KT);
