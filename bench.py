@@ -84,11 +84,11 @@ def cpu_baseline(A, B, C, target_s):
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "strassen_f32_16384_traffic.md")
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary, or None when there is no row for it or
-    the kernel sources changed since the counters were taken (the summary
-    records a sha256 of those sources)."""
+def measured_traffic(kernel, workgroups):
+    """HBM bytes per launch of `kernel` launched with `workgroups` workgroups,
+    from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when
+    there is no row for it or the kernel sources changed since the counters
+    were taken (the summary records a sha256 of those sources)."""
     import hashlib
     import re
     try:
@@ -108,8 +108,8 @@ def measured_traffic(kernel):
         return None
     for line in text.splitlines():
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
-        if len(cells) >= 7 and cells[0] == "`%s`" % kernel:
-            return float(cells[6])
+        if len(cells) >= 8 and cells[0] == "`%s`" % kernel and cells[1] == str(workgroups):
+            return float(cells[7])
     return None
 
 
@@ -338,18 +338,18 @@ def main():
     # device time; achieved = its executed flops / its launch time.
     by_kernel = {}
     for r in headline_records:
-        name = r.kernel.decode()
-        t = by_kernel.setdefault(name, [0.0, 0.0, 0])
+        key = (r.kernel.decode(), r.workgroups)
+        t = by_kernel.setdefault(key, [0.0, 0.0, 0])
         t[0] += r.ms
         t[1] += r.flops
         t[2] += 1
     dom = max(by_kernel.items(), key=lambda kv: kv[1][0])
-    dom_name, (dom_ms, dom_flops, dom_n) = dom
+    (dom_name, dom_wg), (dom_ms, dom_flops, dom_n) = dom
     achieved = dom_flops / (dom_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP32_MFMA_PEAK,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_MFMA_PEAK, 4),
-                "traffic": measured_traffic(dom_name),
-                "kernel": dom_name, "launches": dom_n,
+                "traffic": measured_traffic(dom_name, dom_wg),
+                "kernel": dom_name, "workgroups": dom_wg, "launches": dom_n,
                 "avg_launch_ms": round(dom_ms / dom_n, 4),
                 "flops_per_launch": dom_flops / dom_n}
 
