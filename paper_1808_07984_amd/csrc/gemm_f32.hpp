@@ -26,6 +26,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "launch.hpp"
 
@@ -42,6 +44,14 @@ struct Small {
     static constexpr int GROUP = 8;
 };
 struct Large {
+    static constexpr int MT = 256, NT = 256, KT = 32;
+    static constexpr int WAVES_M = 2, WAVES_N = 4;
+    static constexpr int WAVES_PER_EU = 2;
+    static constexpr int GROUP = 4;
+};
+// Large with a 16-deep k-tile: variants with more than four operand terms in
+// total have no registers for 32-deep staging.
+struct LargeK16 {
     static constexpr int MT = 256, NT = 256, KT = 16;
     static constexpr int WAVES_M = 2, WAVES_N = 4;
     static constexpr int WAVES_PER_EU = 2;
@@ -251,11 +261,11 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
     // A KC operand gives a lane its values for four steps in one 16-byte read;
     // an XC operand is read one 4-byte value per step (32 consecutive x).
     const int h = lane >> 5, l32 = lane & 31;
-    auto compute = [&](int buf) {
+    auto compute = [&](int buf, int c0, int c1) {
         const float *as = &As[buf][0];
         const float *bs = &Bs[buf][0];
 #pragma unroll
-        for (int c = 0; c < KT / 8; ++c) {
+        for (int c = c0; c < c1; ++c) {
             f32x4 af[BM], bf[BN];
 #pragma unroll
             for (int i = 0; i < BM; ++i) {
@@ -298,13 +308,18 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
     for (; kt + 1 < nfast; ++kt) {
         const int cur = kt & 1;
         issue_fast(kt + 1);
-        // Keep the loads ahead of the MFMA block and the sums behind it: left
-        // to itself the scheduler moves them next to each other and exposes
-        // the load latency.
+        // Loads first, then all but the last chunk of MFMAs, then the sums
+        // and LDS stores of the next k-tile (its buffer is idle), then the
+        // last chunk: the loads have most of a k-tile to land, and the MFMA
+        // pipe still has work while the sums are formed.  The scheduling
+        // barriers keep that order (left to itself the scheduler moves the
+        // sums next to the loads and exposes their latency).
         __builtin_amdgcn_sched_barrier(0);
-        compute(cur);
+        compute(cur, 0, KT / 8 - 1);
         __builtin_amdgcn_sched_barrier(0);
         sum_store(cur ^ 1);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(cur, KT / 8 - 1, KT / 8);
         __syncthreads();
     }
     // Remaining k-tiles (fringe workgroups, a ragged last k-tile).
@@ -312,7 +327,7 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
         const int cur = kt & 1;
         const bool more = kt + 1 < nk;
         if (more) issue((kt + 1) * KT);
-        compute(cur);
+        compute(cur, 0, KT / 8);
         if (more) sum_store(cur ^ 1);
         __syncthreads();
     }
@@ -378,10 +393,16 @@ hipError_t launch_variant(const LaunchArgs &a, int batch, bool vec, hipStream_t 
 
 // Concurrent schedule: up to two (one level) or four (two levels) terms per
 // operand and output, counts read per product.
+// Large tiles take the 16-deep k-tile when the variant has more than four
+// operand terms.
+template <class Cfg, int WA, int WB>
+using TileFor = typename std::conditional<std::is_same<Cfg, Large>::value && (WA + WB > 4),
+                                          LargeK16, Cfg>::type;
+
 template <class Cfg>
 hipError_t dispatch_concurrent(int wmax, const LaunchArgs &a, int batch, bool vec, hipStream_t s) {
-    if (wmax <= 2) return launch_variant<Cfg, true, false, 2, 2, 2, true>(a, batch, vec, s);
-    return launch_variant<Cfg, true, false, 4, 4, 4, true>(a, batch, vec, s);
+    if (wmax <= 2) return launch_variant<TileFor<Cfg, 2, 2>, true, false, 2, 2, 2, true>(a, batch, vec, s);
+    return launch_variant<TileFor<Cfg, 4, 4>, true, false, 4, 4, 4, true>(a, batch, vec, s);
 }
 
 template <class Cfg, bool A_KC, bool B_KC>
@@ -389,7 +410,7 @@ hipError_t dispatch(int wa, int wb, int wc, const LaunchArgs &a, int batch, bool
                     hipStream_t s) {
 #define STRASSEN_CASE(X, Y, Z)        \
     if (wa == X && wb == Y && wc == Z) \
-        return launch_variant<Cfg, A_KC, B_KC, X, Y, Z>(a, batch, vec, s);
+        return launch_variant<TileFor<Cfg, X, Y>, A_KC, B_KC, X, Y, Z>(a, batch, vec, s);
     // plain GEMM and the one-level variants
     STRASSEN_CASE(1, 1, 1)
     STRASSEN_CASE(2, 2, 2)

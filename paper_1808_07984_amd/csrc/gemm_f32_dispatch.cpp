@@ -4,7 +4,8 @@
 namespace strassen {
 
 KernelShape f32_tile_shape(bool large) {
-    return large ? KernelShape{256, 256, 16, 4} : KernelShape{128, 128, 32, 4};
+    // k-tile of the variants with at most four operand terms (more: 16)
+    return large ? KernelShape{256, 256, 32, 4} : KernelShape{128, 128, 32, 4};
 }
 
 hipError_t launch_f32(bool trans_a, bool trans_b, bool large, int wa, int wb, int wc,
