@@ -40,7 +40,7 @@ LAUNCH_S = 6e-6
 
 TILES = {  # (MT, NT, KT, waves, workgroups per CU)
     ("f32", False): (128, 128, 32, 4, 2),
-    ("f32", True): (256, 256, 16, 8, 1),
+    ("f32", True): (256, 256, 32, 8, 1),   # KT 16 above four operand terms
     ("16bit", False): (128, 128, 32, 4, 2),
     ("16bit", True): (256, 256, 32, 8, 1),
     ("x3", False): (128, 128, 32, 4, 2),
@@ -84,6 +84,8 @@ def predict(m, n, k, levels, kind="f32"):
     for wa, wb, wc, batch in _batches(levels):
         large = _use_large(sm, sn, batch)
         mt, nt, kt, waves, slots_per_cu = TILES[(kind, large)]
+        if kind == "f32" and large and wa + wb > 4:
+            kt = 16
         tiles = math.ceil(sm / mt) * math.ceil(sn / nt) * batch
         ktiles = math.ceil(sk / kt)
         wm, wn = (mt // 2, nt // (waves // 2))

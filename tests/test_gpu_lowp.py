@@ -91,6 +91,37 @@ def test_bf16x3_far_more_accurate_than_bf16(levels):
     assert err3 * 32 <= errb
 
 
+@pytest.mark.parametrize("kind", ["bf16", "f16"])
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_lowp_scaled_rows_and_columns(kind, levels):
+    """Rows of A and columns of B with 2-norms 10^u, u ~ U[-3, 3] (the
+    precision workload's scaled variant).  Strassen's error bound is normwise:
+    the gate is e_norm <= tau_L.  Without operand sums (L = 0) the error of
+    each entry is also within the gate relative to its own row and column
+    (componentwise); at L >= 1 a sum mixes rows of different blocks, so only
+    the normwise bound is claimed and the row-relative error is reported."""
+    from paper_1808_07984_amd import inputs
+    dtype = MODES[kind][0]
+    tdt = {"bf16": torch.bfloat16, "f16": torch.float16}[kind]
+    m = n = k = 1536
+    A = inputs.scaled(m, k, inputs.SEED_A, axis=0, dtype=tdt)
+    B = inputs.scaled(k, n, inputs.SEED_B, axis=1, dtype=tdt)
+    prob = dict(A=A, B=B, C=torch.zeros(m, n), lda=k, ldb=n, ldc=n, fill=float("nan"))
+    dev = _run(prob, levels, 1.0, 0.0, "plain")
+    want = oracle.gemm_f64(A, B)
+    got = dev["C"].cpu().double().numpy()
+    en = e_norm(got, want, A, B, None, k, 1.0, 0.0, GATE_EPS[kind])
+    ra = np.abs(oracle._f64(A)).max(axis=1)
+    cb = np.abs(oracle._f64(B)).max(axis=0)
+    comp = np.abs(got - want) / (GATE_EPS[kind] * k * np.outer(ra, cb))
+    rel_fro = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print("e_norm %.4f  componentwise max %.4f  relative Frobenius %.3e" % (en, comp.max(), rel_fro),
+          flush=True)
+    assert en <= tau(levels)
+    if levels == 0:
+        assert comp.max() <= tau(0)
+
+
 def test_lowp_deterministic():
     prob = make_problem(600, 520, 700, kind="normal", dtype="bf16", c_kind="uniform")
     d1 = _run(prob, 2, 1.0, 1.0, "plain")

@@ -199,6 +199,19 @@ def test_full_size_square_16384(levels):
     _sampled(16384, 16384, 16384, levels, 1.0, 1.0)
 
 
+@pytest.mark.parametrize("k", [512, 4096])
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_full_size_rank_k(k, levels):
+    """Rank-k updates m = n = 16384 (k = 512 at two levels: 128-deep blocks,
+    fewer than one 256-row k-slab of the plain kernel)."""
+    _sampled(16384, 16384, k, levels, 1.0, 1.0)
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_full_size_square_12288(levels):
+    _sampled(12288, 12288, 12288, levels, 1.0, 1.0)
+
+
 @pytest.mark.parametrize("levels", [2])
 def test_full_size_awkward_15001(levels):
     _sampled(15001, 17003, 9007, levels, 1.5, 0.5, lda=9024, ldb=17024, ldc=17024)

@@ -1,0 +1,70 @@
+"""The performance model (Analysis section, T = max of the resource times per
+launch, plus wave quantisation and launch overhead) against facts it must
+reproduce: the flop term is the executed MFMA work of the plan, launches are
+the plan's race-free batches, small problems lose to quantisation, and the
+16-bit two-level path leaves the MFMA bound (the fetch form of eq.
+constrain_glb).  Host only: plan queries need no GPU."""
+import math
+
+import pytest
+
+import paper_1808_07984_amd as sg
+from paper_1808_07984_amd import model
+
+
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_launches_are_the_plans_batches(levels):
+    rc, info = sg.strassen_plan_info(4096, 4096, 4096, levels)
+    assert rc == 0
+    _, launches = model.predict(4096, 4096, 4096, levels)
+    assert len(launches) == info.n_launches == [1, 4, 16][levels]
+    assert sum(l["batch"] for l in launches) == 7 ** levels
+
+
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_flop_term_is_executed_mfma_work(levels):
+    """Full tiles at 16384: sum over launches of t_flop x MFMA rate equals the
+    plan's executed flops 7^L * 2 * s^3."""
+    n = 16384
+    _, info = sg.strassen_plan_info(n, n, n, levels)
+    _, launches = model.predict(n, n, n, levels)
+    rate = model.CUS * model.MFMA_FLOP_PER_CLK_CU["f32"] * model.CLOCK_HZ
+    flops = sum(l["t_flop"] for l in launches) * rate
+    assert math.isclose(flops, info.executed_flops, rel_tol=1e-12)
+    assert all(l["bound"] == "flop" for l in launches)
+
+
+def test_plain_gemm_time_is_flops_over_peak():
+    n = 16384
+    t, (l,) = model.predict(n, n, n, 0)
+    ideal = 2.0 * n ** 3 / (model.CUS * model.MFMA_FLOP_PER_CLK_CU["f32"] * model.CLOCK_HZ)
+    assert l["quantisation"] == 1.0
+    assert math.isclose(t, ideal + model.LAUNCH_S, rel_tol=1e-12)
+
+
+def test_strassen_pays_at_large_sizes_only():
+    """fp32: one level predicted faster than plain at 16384, slower at 1024
+    (fewer, emptier launches: wave quantisation and launch overhead)."""
+    big0, _ = model.predict(16384, 16384, 16384, 0)
+    big1, _ = model.predict(16384, 16384, 16384, 1)
+    small0, _ = model.predict(1024, 1024, 1024, 0)
+    small1, ls = model.predict(1024, 1024, 1024, 1)
+    assert big1 < big0 * 7 / 8 * 1.01
+    assert small1 > small0
+    assert any(l["quantisation"] > 1.0 for l in ls)
+
+
+def test_16bit_two_level_leaves_the_mfma_bound():
+    """At 16384 the 16-bit two-level launches are bound by HBM or L2->CU
+    operand traffic, while fp32 stays MFMA bound at every level."""
+    _, ls = model.predict(16384, 16384, 16384, 2, "16bit")
+    assert any(l["bound"] in ("hbm", "l2") for l in ls)
+    _, l0 = model.predict(16384, 16384, 16384, 0, "16bit")
+    assert l0[0]["bound"] in ("flop", "lds")
+
+
+def test_compensated_mode_triples_the_flop_term():
+    n = 8192
+    _, f = model.predict(n, n, n, 0, "16bit")
+    _, x = model.predict(n, n, n, 0, "x3")
+    assert math.isclose(x[0]["t_flop"], 3 * f[0]["t_flop"], rel_tol=1e-12)
