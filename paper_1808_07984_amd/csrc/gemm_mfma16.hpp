@@ -36,6 +36,9 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 // Tile shapes.  LDS row strides are in 16-bit elements: direct tiles use
@@ -67,6 +70,10 @@ struct Bf16Ops {
     __device__ static unsigned short from_f32(float f) {
         return __builtin_bit_cast(unsigned short, (__bf16)f);
     }
+    // (lo, hi) rounded to nearest even and packed into one word
+    __device__ static unsigned pack2(float lo, float hi) {
+        return __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{lo, hi}, bf16x2));
+    }
 };
 struct F16Ops {
     using In = unsigned short;  // raw fp16 bits
@@ -78,6 +85,9 @@ struct F16Ops {
     }
     __device__ static unsigned short from_f32(float f) {
         return __builtin_bit_cast(unsigned short, (_Float16)f);
+    }
+    __device__ static unsigned pack2(float lo, float hi) {
+        return __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{lo, hi}, f16x2));
     }
 };
 struct X3Ops {
@@ -91,6 +101,9 @@ struct X3Ops {
     }
     __device__ static float bf16_to_f32(unsigned short h) {
         return __uint_as_float((unsigned)h << 16);
+    }
+    __device__ static unsigned pack2(float lo, float hi) {
+        return __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{lo, hi}, bf16x2));
     }
 };
 
@@ -284,13 +297,32 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
         }
     };
 
-    // Signed sum of element e of load l of unit p over the terms, in fp32.
-    auto sum_elem = [&](auto &raw, const TermArg *terms, auto nterms, int p, int l, int e) __attribute__((always_inline)) {
+    // Sign of the first term of each operand: factored out of the operand
+    // sum and applied in the epilogue instead (signs are +-1 and rounding to
+    // nearest even is symmetric, so the staged values are the same up to
+    // that exact negation).  The staged sum is x_0 + sum_t (s_t s_0) x_t.
+    const float sa0 = P.a[0].sign, sb0 = P.b[0].sign;
+
+    // Relative-signed sum of element e of load l of unit p over the terms,
+    // in fp32.
+    auto sum_elem = [&](auto &raw, const TermArg *terms, float s0, auto nterms, int p, int l, int e) __attribute__((always_inline)) {
         constexpr int NT_ = decltype(nterms)::value;
-        float s = terms[0].sign * Ops::to_f32(raw[0][p][l][e]);
+        float s = Ops::to_f32(raw[0][p][l][e]);
 #pragma unroll
-        for (int t = 1; t < NT_; ++t) s += terms[t].sign * Ops::to_f32(raw[t][p][l][e]);
+        for (int t = 1; t < NT_; ++t) s += (terms[t].sign * s0) * Ops::to_f32(raw[t][p][l][e]);
         return s;
+    };
+
+    // One stored operand value needs no arithmetic: its bits go to LDS as
+    // they are (the 16-bit operand types only; the compensated mode splits).
+    constexpr bool kCopyA = WA == 1 && !Ops::kX3;
+    constexpr bool kCopyB = WB == 1 && !Ops::kX3;
+
+    // Paired layout from raw rows k and k+1 of NV consecutive x: the word of
+    // x + 2j (x + 2j + 1) holds the low (high) halves of word j of both rows.
+    auto pair_words = [&](const V &row0, const V &row1, int e) __attribute__((always_inline)) -> unsigned {
+        const u32x4 r0 = __builtin_bit_cast(u32x4, row0), r1 = __builtin_bit_cast(u32x4, row1);
+        return __builtin_amdgcn_perm(r1[e >> 1], r0[e >> 1], (e & 1) ? 0x07060302u : 0x05040100u);
     };
 
     // Signed sums rounded to the MFMA type (split into hi/lo for the
@@ -301,12 +333,14 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
         for (int p = 0; p < SA::VECS; ++p) {
             int x, k;
             SA::coords(tid, p, x, k);
-            if constexpr (A_KC) {
+            if constexpr (A_KC && kCopyA) {
+                *reinterpret_cast<V *>(&As[buf][0][x * SA::LDX + k]) = raw_a[0][p][0];
+            } else if constexpr (A_KC) {
                 // direct: NV consecutive k of row x
                 unsigned short hi[NV], lo[NV];
 #pragma unroll
                 for (int e = 0; e < NV; ++e) {
-                    const float s = sum_elem(raw_a, P.a, std::integral_constant<int, WA>{}, p, 0, e);
+                    const float s = sum_elem(raw_a, P.a, sa0, std::integral_constant<int, WA>{}, p, 0, e);
                     hi[e] = Ops::from_f32(s);
                     if constexpr (Ops::kX3) lo[e] = Ops::from_f32(s - Ops::bf16_to_f32(hi[e]));
                 }
@@ -326,20 +360,24 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
                         *reinterpret_cast<u16x4 *>(&As[buf][q][off]) = w;
                     }
                 }
+            } else if constexpr (kCopyA) {
+#pragma unroll
+                for (int e = 0; e < NV; ++e)
+                    *reinterpret_cast<unsigned *>(&As[buf][0][(x + e) * SA::LDX + k]) =
+                        pair_words(raw_a[0][p][0], raw_a[0][p][1], e);
             } else {
                 // paired: k rows k, k+1 of NV consecutive x
 #pragma unroll
                 for (int e = 0; e < NV; ++e) {
-                    const float s0 = sum_elem(raw_a, P.a, std::integral_constant<int, WA>{}, p, 0, e);
-                    const float s1 = sum_elem(raw_a, P.a, std::integral_constant<int, WA>{}, p, 1, e);
-                    const unsigned short h0 = Ops::from_f32(s0), h1 = Ops::from_f32(s1);
+                    const float s0 = sum_elem(raw_a, P.a, sa0, std::integral_constant<int, WA>{}, p, 0, e);
+                    const float s1 = sum_elem(raw_a, P.a, sa0, std::integral_constant<int, WA>{}, p, 1, e);
+                    const unsigned hw = Ops::pack2(s0, s1);
                     const int off = (x + e) * SA::LDX + k;
-                    *reinterpret_cast<unsigned *>(&As[buf][0][off]) = (unsigned)h0 | ((unsigned)h1 << 16);
+                    *reinterpret_cast<unsigned *>(&As[buf][0][off]) = hw;
                     if constexpr (Ops::kX3) {
-                        const unsigned short l0 = Ops::from_f32(s0 - Ops::bf16_to_f32(h0));
-                        const unsigned short l1 = Ops::from_f32(s1 - Ops::bf16_to_f32(h1));
-                        *reinterpret_cast<unsigned *>(&As[buf][NPLANES - 1][off]) =
-                            (unsigned)l0 | ((unsigned)l1 << 16);
+                        const float r0 = s0 - __uint_as_float(hw << 16);
+                        const float r1 = s1 - __uint_as_float(hw & 0xffff0000u);
+                        *reinterpret_cast<unsigned *>(&As[buf][NPLANES - 1][off]) = Ops::pack2(r0, r1);
                     }
                 }
             }
@@ -349,11 +387,13 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
         for (int p = 0; p < SB::VECS; ++p) {
             int x, k;
             SB::coords(tid, p, x, k);
-            if constexpr (B_KC) {
+            if constexpr (B_KC && kCopyB) {
+                *reinterpret_cast<V *>(&Bs[buf][0][x * SB::LDX + k]) = raw_b[0][p][0];
+            } else if constexpr (B_KC) {
                 unsigned short hi[NV], lo[NV];
 #pragma unroll
                 for (int e = 0; e < NV; ++e) {
-                    const float s = sum_elem(raw_b, P.b, std::integral_constant<int, WB>{}, p, 0, e);
+                    const float s = sum_elem(raw_b, P.b, sb0, std::integral_constant<int, WB>{}, p, 0, e);
                     hi[e] = Ops::from_f32(s);
                     if constexpr (Ops::kX3) lo[e] = Ops::from_f32(s - Ops::bf16_to_f32(hi[e]));
                 }
@@ -373,19 +413,23 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
                         *reinterpret_cast<u16x4 *>(&Bs[buf][q][off]) = w;
                     }
                 }
+            } else if constexpr (kCopyB) {
+#pragma unroll
+                for (int e = 0; e < NV; ++e)
+                    *reinterpret_cast<unsigned *>(&Bs[buf][0][(x + e) * SB::LDX + k]) =
+                        pair_words(raw_b[0][p][0], raw_b[0][p][1], e);
             } else {
 #pragma unroll
                 for (int e = 0; e < NV; ++e) {
-                    const float s0 = sum_elem(raw_b, P.b, std::integral_constant<int, WB>{}, p, 0, e);
-                    const float s1 = sum_elem(raw_b, P.b, std::integral_constant<int, WB>{}, p, 1, e);
-                    const unsigned short h0 = Ops::from_f32(s0), h1 = Ops::from_f32(s1);
+                    const float s0 = sum_elem(raw_b, P.b, sb0, std::integral_constant<int, WB>{}, p, 0, e);
+                    const float s1 = sum_elem(raw_b, P.b, sb0, std::integral_constant<int, WB>{}, p, 1, e);
+                    const unsigned hw = Ops::pack2(s0, s1);
                     const int off = (x + e) * SB::LDX + k;
-                    *reinterpret_cast<unsigned *>(&Bs[buf][0][off]) = (unsigned)h0 | ((unsigned)h1 << 16);
+                    *reinterpret_cast<unsigned *>(&Bs[buf][0][off]) = hw;
                     if constexpr (Ops::kX3) {
-                        const unsigned short l0 = Ops::from_f32(s0 - Ops::bf16_to_f32(h0));
-                        const unsigned short l1 = Ops::from_f32(s1 - Ops::bf16_to_f32(h1));
-                        *reinterpret_cast<unsigned *>(&Bs[buf][NPLANES - 1][off]) =
-                            (unsigned)l0 | ((unsigned)l1 << 16);
+                        const float r0 = s0 - __uint_as_float(hw << 16);
+                        const float r1 = s1 - __uint_as_float(hw & 0xffff0000u);
+                        *reinterpret_cast<unsigned *>(&Bs[buf][NPLANES - 1][off]) = Ops::pack2(r0, r1);
                     }
                 }
             }
@@ -488,7 +532,7 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
     int crows[WC], ccols[WC], cfirst[WC];
 #pragma unroll
     for (int o = 0; o < WC; ++o) {
-        g[o] = P.c[o].sign * alpha;
+        g[o] = P.c[o].sign * (sa0 * sb0) * alpha;
         coff[o] = P.c[o].off;
         crows[o] = P.c[o].rows;
         ccols[o] = P.c[o].cols;
