@@ -168,7 +168,8 @@ typedef struct {
     int32_t n_launches;        /* race-free batches = kernel launches */
     int32_t tile_m, tile_n, tile_k; /* workgroup tile of the product kernel (tile_k:
                                      * variants with at most four operand terms;
-                                     * the fp32 256x256 kernels use 16 above) */
+                                     * above that the 256x256 fp32 kernels use 16,
+                                     * the 16-bit ones 32) */
     int32_t workgroups_per_instance;
     double executed_flops;     /* 7^L * 2 * sub_m * sub_n * sub_k */
     double classical_flops;    /* 2 * m * n * k */

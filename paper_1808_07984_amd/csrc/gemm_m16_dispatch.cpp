@@ -5,7 +5,8 @@ namespace strassen {
 
 KernelShape m16_tile_shape(bool x3, bool large) {
     // 16-byte loads cover 8 elements of a 16-bit type or 4 fp32.
-    if (large) return KernelShape{256, 256, x3 ? 16 : 32, x3 ? 4 : 8};
+    // k-tile of the variants with at most four operand terms (more: 32)
+    if (large) return KernelShape{256, 256, x3 ? 16 : 64, x3 ? 4 : 8};
     return KernelShape{128, 128, 32, x3 ? 4 : 8};
 }
 

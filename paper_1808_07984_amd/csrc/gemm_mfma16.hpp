@@ -58,6 +58,7 @@ struct Cfg {
 };
 using Small = Cfg<128, 128, 32, 2, 2, 8>;
 using Large = Cfg<256, 256, 32, 2, 4, 4>;     // 16-bit operands
+using LargeK64 = Cfg<256, 256, 64, 2, 4, 4>;  // 16-bit operands, at most four terms
 using LargeX3 = Cfg<256, 256, 16, 2, 4, 4>;   // fp32 operands split hi/lo
 
 // Operand types.
@@ -573,12 +574,20 @@ hipError_t launch_variant(const LaunchArgs &a, int batch, bool vec, hipStream_t 
     return hipGetLastError();
 }
 
+// 16-bit large tiles stage 64-deep k-tiles when the variant has at most four
+// operand terms: one k-tile is then about 2000 MFMA cycles per SIMD, which
+// amortises the barrier and the first LDS reads of each k-tile; with more
+// terms the staging registers allow 32.
+template <class C, class Ops, int WA, int WB>
+using TileFor = typename std::conditional<std::is_same<C, Large>::value && !Ops::kX3 && WA + WB <= 4,
+                                          LargeK64, C>::type;
+
 template <class C, class Ops, bool A_KC, bool B_KC>
 hipError_t dispatch(int wa, int wb, int wc, const LaunchArgs &a, int batch, bool vec,
                     hipStream_t s) {
 #define STRASSEN_CASE(X, Y, Z)        \
     if (wa == X && wb == Y && wc == Z) \
-        return launch_variant<C, Ops, A_KC, B_KC, X, Y, Z>(a, batch, vec, s);
+        return launch_variant<TileFor<C, Ops, X, Y>, Ops, A_KC, B_KC, X, Y, Z>(a, batch, vec, s);
     STRASSEN_CASE(1, 1, 1)
     STRASSEN_CASE(2, 2, 2)
     STRASSEN_CASE(2, 2, 1)
