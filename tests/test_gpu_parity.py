@@ -229,6 +229,57 @@ def test_full_size_awkward_integer_exact():
              kind="integers", exact=True)
 
 
+def _wide(x, ld):
+    """Device view of x inside a rows x ld storage whose tail is NaN, built on
+    the device (the storages here are several GiB)."""
+    st = torch.full((x.shape[0], ld), float("nan"), dtype=x.dtype, device="cuda")
+    st[:, : x.shape[1]] = x.cuda()
+    return st[:, : x.shape[1]]
+
+
+@pytest.fixture
+def tile256():
+    assert sg.strassen_set_tile(sg.STRASSEN_TILE_256) == 0
+    yield
+    sg.strassen_set_tile(sg.STRASSEN_TILE_AUTO)
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("kind,levels", [("f32", 0), ("f32", 1), ("bf16", 0), ("bf16", 1)])
+def test_a_leading_dimension_past_32bit_tile_offsets(tile256, kind, levels):
+    """lda so large that 256 rows of A span more than 2^32 bytes: the
+    in-bounds loop addresses a tile with 32-bit per-thread byte offsets, so
+    these calls must take the guarded loop, and stay exact."""
+    esz = 4 if kind == "f32" else 2
+    lda = (1 << 32) // (256 * esz) + 8
+    m, n, k = 256 << levels, 256 << levels, 64 << levels
+    prob = make_problem(m, n, k, kind="integers", dtype=kind, c_kind="integers")
+    A = _wide(prob["A"], lda)
+    B, C = prob["B"].cuda(), prob["C"].cuda()
+    print("case lda=%d m=%d n=%d k=%d L=%d %s" % (lda, m, n, k, levels, kind), flush=True)
+    sg.gemm(A, B, C, 1.0, 1.0, levels=levels)
+    torch.cuda.synchronize()
+    want = oracle.gemm_f64(prob["A"], prob["B"], prob["C"], 1.0, 1.0)
+    assert np.array_equal(C.cpu().double().numpy(), want)
+
+
+@pytest.mark.parametrize("kind", ["f32", "bf16"])
+def test_b_leading_dimension_past_32bit_tile_offsets(tile256, kind):
+    """ldb so large that one k-tile of B rows spans more than 2^32 bytes."""
+    esz = 4 if kind == "f32" else 2
+    kt = 32 if kind == "f32" else 64
+    ldb = (1 << 32) // (kt * esz) + 8
+    m, n, k = 256, 256, 2 * kt
+    prob = make_problem(m, n, k, kind="integers", dtype=kind, c_kind="integers")
+    B = _wide(prob["B"], ldb)
+    A, C = prob["A"].cuda(), prob["C"].cuda()
+    print("case ldb=%d m=%d n=%d k=%d %s" % (ldb, m, n, k, kind), flush=True)
+    sg.gemm(A, B, C, 1.0, 1.0, levels=0)
+    torch.cuda.synchronize()
+    want = oracle.gemm_f64(prob["A"], prob["B"], prob["C"], 1.0, 1.0)
+    assert np.array_equal(C.cpu().double().numpy(), want)
+
+
 @pytest.fixture
 def tile_mode(request):
     """Forces the fp32 tile shape for one test, then restores automatic."""
