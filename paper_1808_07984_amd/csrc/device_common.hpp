@@ -34,6 +34,19 @@ __device__ __forceinline__ void tile_coords(int tiles_m, int tiles_n, int &tm, i
     tn = in / gs;
 }
 
+// 16-byte loads through a buffer resource: the base lives in scalar
+// registers and each lane supplies a 32-bit byte offset, so a load costs no
+// 64-bit address registers.  The record count is 2^32 - 1: no range
+// clamping; callers keep every offset (plus 16) below 2^32.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void *base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, -1, 0x00020000);
+}
+template <class V>
+__device__ __forceinline__ V buffer_load16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    static_assert(sizeof(V) == 16, "16-byte vectors");
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
 // Smallest extent over the first n terms (scalar, uniform).
 __device__ __forceinline__ void min_extent(const TermArg *t, int n, int &rows, int &cols) {
     rows = t[0].rows;

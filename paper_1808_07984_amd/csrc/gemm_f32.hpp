@@ -157,9 +157,9 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
     f32x4 raw_b[WB][SB::VECS];
 
     // In-bounds k-tiles: loads of k-tiles [0, nfast) need no guard.  They
-    // address each term from a uniform base pointer (scalar registers,
-    // advanced one k-tile per step) plus a per-thread 32-bit byte offset that
-    // does not change along k.
+    // are buffer loads: each term's base (scalar registers, advanced one
+    // k-tile per step) plus a per-thread 32-bit byte offset that does not
+    // change along k.
     constexpr uint64_t kOffLimit = 1ull << 32;
     const bool a_off32 = (uint64_t)(A_KC ? MT : KT) * (uint64_t)lda * 4u < kOffLimit;
     const bool b_off32 = (uint64_t)(B_KC ? NT : KT) * (uint64_t)ldb * 4u < kOffLimit;
@@ -187,19 +187,19 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
 #pragma unroll
         for (int t = 0; t < WA; ++t) {
             if (t < na) {
-                const char *base = reinterpret_cast<const char *>(A + P.a[t].off + a_org) + a_step * kt;
+                const auto r = raw_rsrc(reinterpret_cast<const char *>(A + P.a[t].off + a_org) +
+                                        a_step * kt);
 #pragma unroll
-                for (int p = 0; p < SA::VECS; ++p)
-                    raw_a[t][p] = *reinterpret_cast<const f32x4 *>(base + a_off[p]);
+                for (int p = 0; p < SA::VECS; ++p) raw_a[t][p] = buffer_load16<f32x4>(r, a_off[p]);
             }
         }
 #pragma unroll
         for (int t = 0; t < WB; ++t) {
             if (t < nb) {
-                const char *base = reinterpret_cast<const char *>(B + P.b[t].off + b_org) + b_step * kt;
+                const auto r = raw_rsrc(reinterpret_cast<const char *>(B + P.b[t].off + b_org) +
+                                        b_step * kt);
 #pragma unroll
-                for (int p = 0; p < SB::VECS; ++p)
-                    raw_b[t][p] = *reinterpret_cast<const f32x4 *>(base + b_off[p]);
+                for (int p = 0; p < SB::VECS; ++p) raw_b[t][p] = buffer_load16<f32x4>(r, b_off[p]);
             }
         }
     };

@@ -245,7 +245,10 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
 
     // In-bounds k-tiles [0, nfast): unguarded loads from a uniform per-term
     // base (advanced one k-tile per step) plus a per-thread 32-bit byte
-    // offset that does not change along k.
+    // offset that does not change along k.  Single-term operands use buffer
+    // loads (measured faster); with more terms plain global loads measured
+    // faster here.
+    constexpr bool kBufferLoads = WA + WB <= 2;
     constexpr uint64_t kOffLimit = 1ull << 32;
     const bool off32 = (uint64_t)(A_KC ? C::MT : C::KT) * (uint64_t)lda * sizeof(In) < kOffLimit &&
                        (uint64_t)(B_KC ? C::NT : C::KT) * (uint64_t)ldb * sizeof(In) < kOffLimit;
@@ -284,11 +287,19 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
 #pragma unroll
         for (int t = 0; t < NT_; ++t) {
             const char *tb = reinterpret_cast<const char *>(base + terms[t].off + org) + step * kt;
+            if constexpr (kBufferLoads) {
+                const auto r = raw_rsrc(tb);
 #pragma unroll
-            for (int p = 0; p < S::VECS; ++p)
+                for (int p = 0; p < S::VECS; ++p)
 #pragma unroll
-                for (int l = 0; l < S::LOADS; ++l)
-                    raw[t][p][l] = *reinterpret_cast<const V *>(tb + off[p][l]);
+                    for (int l = 0; l < S::LOADS; ++l) raw[t][p][l] = buffer_load16<V>(r, off[p][l]);
+            } else {
+#pragma unroll
+                for (int p = 0; p < S::VECS; ++p)
+#pragma unroll
+                    for (int l = 0; l < S::LOADS; ++l)
+                        raw[t][p][l] = *reinterpret_cast<const V *>(tb + off[p][l]);
+            }
         }
     };
     auto stage_load_fast = [&](int kt) __attribute__((always_inline)) {
