@@ -58,6 +58,34 @@ struct LargeK16 {
     static constexpr int GROUP = 4;
 };
 
+// Staging of an m/n-contiguous operand kept [x][k] in LDS instead ("XT"),
+// so that its fragments are 16-byte reads like a k-contiguous operand's.
+// Each thread loads 4 consecutive k rows of one 4-wide x quad (every load
+// instruction still covers whole rows across the wave) and stores the
+// transposed 4x4 block as four 16-byte rows.  The 4-wide k group is XOR
+// swizzled by x / 8: with the row stride KT + 4 this keeps both the stores
+// and the fragment reads free of bank conflicts (32 banks, 8 lanes per
+// 16-byte access).
+template <int X, int KT, int THREADS>
+struct StageXT {
+    static constexpr int LDX = KT + 4;
+    static constexpr int SIZE = X * LDX;
+    static constexpr int VECS = X * KT / 4 / THREADS;  // float4 per thread per term
+    static constexpr int QX = X / 4;                   // x quads per k row
+    static constexpr int NG = KT / 4;                  // k groups
+    static constexpr int GSTEP = THREADS / QX;         // k groups per 4 loads
+    static_assert(VECS % 4 == 0 && THREADS % QX == 0, "whole 4x4 blocks");
+    static_assert((NG & (NG - 1)) == 0, "power-of-two k groups");
+
+    // Load p of thread tid: first x of the quad and its k row.
+    __device__ static void coords(int tid, int p, int &x, int &k) {
+        x = (tid % QX) * 4;
+        k = 4 * (tid / QX + (p / 4) * GSTEP) + (p % 4);
+    }
+    // LDS offset of element (x, k), k a multiple of 4 (start of a group).
+    __device__ static int lds(int x, int k) { return x * LDX + 4 * ((k / 4) ^ ((x / 8) % NG)); }
+};
+
 // Staging geometry of one operand tile of X x KT elements.
 template <int X, int KT, int THREADS, bool KC>
 struct Stage {
@@ -122,8 +150,15 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
     constexpr int THREADS = 64 * Cfg::WAVES_M * Cfg::WAVES_N;
     constexpr int WM = MT / Cfg::WAVES_M, WN = NT / Cfg::WAVES_N;  // wave tile
     constexpr int BM = WM / 32, BN = WN / 32;  // 32x32 MFMA blocks per wave
-    using SA = Stage<MT, KT, THREADS, A_KC>;
-    using SB = Stage<NT, KT, THREADS, B_KC>;
+    // m/n-contiguous operands are kept [x][k] (StageXT) in variants with at
+    // least three operand terms, where the 16-byte fragment reads measured
+    // faster (+4 % for (2,2,1)); with one term each the [k][x] layout is
+    // slightly faster.
+    constexpr bool XT_VARIANT = WA + WB >= 3;
+    constexpr bool A_XT = !A_KC && XT_VARIANT && (MT * KT / 4 / THREADS) % 4 == 0;
+    constexpr bool B_XT = !B_KC && XT_VARIANT && (NT * KT / 4 / THREADS) % 4 == 0;
+    using SA = typename std::conditional<A_XT, StageXT<MT, KT, THREADS>, Stage<MT, KT, THREADS, A_KC>>::type;
+    using SB = typename std::conditional<B_XT, StageXT<NT, KT, THREADS>, Stage<NT, KT, THREADS, B_KC>>::type;
     static_assert(KT % 8 == 0, "k chunks of 8");
 
     __shared__ __attribute__((aligned(16))) float As[2][SA::SIZE];
@@ -227,27 +262,43 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
     };
 
     // Form the signed operand sums and store them into LDS buffer `buf`.
+    auto store_operand = [&](auto stage, auto xt, float *tile, f32x4 (*raw)[decltype(stage)::VECS],
+                             auto nterms, int n_use, const TermArg *terms) {
+        using S = decltype(stage);
+        constexpr int NT_ = decltype(nterms)::value;
+        auto sum = [&](int p) {
+            f32x4 v = raw[0][p] * terms[0].sign;
+#pragma unroll
+            for (int t = 1; t < NT_; ++t)
+                if (t < n_use) v += raw[t][p] * terms[t].sign;
+            return v;
+        };
+        if constexpr (decltype(xt)::value) {
+#pragma unroll
+            for (int p0 = 0; p0 < S::VECS; p0 += 4) {
+                const f32x4 r0 = sum(p0), r1 = sum(p0 + 1), r2 = sum(p0 + 2), r3 = sum(p0 + 3);
+                int x, k;
+                S::coords(tid, p0, x, k);
+                *reinterpret_cast<f32x4 *>(&tile[S::lds(x + 0, k)]) = f32x4{r0[0], r1[0], r2[0], r3[0]};
+                *reinterpret_cast<f32x4 *>(&tile[S::lds(x + 1, k)]) = f32x4{r0[1], r1[1], r2[1], r3[1]};
+                *reinterpret_cast<f32x4 *>(&tile[S::lds(x + 2, k)]) = f32x4{r0[2], r1[2], r2[2], r3[2]};
+                *reinterpret_cast<f32x4 *>(&tile[S::lds(x + 3, k)]) = f32x4{r0[3], r1[3], r2[3], r3[3]};
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < S::VECS; ++p) {
+                const f32x4 v = sum(p);
+                int x, k;
+                S::coords(tid, p, x, k);
+                *reinterpret_cast<f32x4 *>(&tile[S::lds(x, k)]) = v;
+            }
+        }
+    };
     auto sum_store = [&](int buf) {
-#pragma unroll
-        for (int p = 0; p < SA::VECS; ++p) {
-            f32x4 s = raw_a[0][p] * P.a[0].sign;
-#pragma unroll
-            for (int t = 1; t < WA; ++t)
-                if (t < na) s += raw_a[t][p] * P.a[t].sign;
-            int x, k;
-            SA::coords(tid, p, x, k);
-            *reinterpret_cast<f32x4 *>(&As[buf][SA::lds(x, k)]) = s;
-        }
-#pragma unroll
-        for (int p = 0; p < SB::VECS; ++p) {
-            f32x4 s = raw_b[0][p] * P.b[0].sign;
-#pragma unroll
-            for (int t = 1; t < WB; ++t)
-                if (t < nb) s += raw_b[t][p] * P.b[t].sign;
-            int x, k;
-            SB::coords(tid, p, x, k);
-            *reinterpret_cast<f32x4 *>(&Bs[buf][SB::lds(x, k)]) = s;
-        }
+        store_operand(SA{}, std::integral_constant<bool, A_XT>{}, &As[buf][0], raw_a,
+                      std::integral_constant<int, WA>{}, na, P.a);
+        store_operand(SB{}, std::integral_constant<bool, B_XT>{}, &Bs[buf][0], raw_b,
+                      std::integral_constant<int, WB>{}, nb, P.b);
     };
 
     f32x16 acc[BM][BN];
@@ -270,7 +321,7 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
 #pragma unroll
             for (int i = 0; i < BM; ++i) {
                 const int x = wm * WM + i * 32 + l32;
-                if (A_KC)
+                if (A_KC || A_XT)
                     af[i] = *reinterpret_cast<const f32x4 *>(&as[SA::lds(x, c * 8 + h * 4)]);
                 else
 #pragma unroll
@@ -279,7 +330,7 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
 #pragma unroll
             for (int j = 0; j < BN; ++j) {
                 const int x = wn * WN + j * 32 + l32;
-                if (B_KC)
+                if (B_KC || B_XT)
                     bf[j] = *reinterpret_cast<const f32x4 *>(&bs[SB::lds(x, c * 8 + h * 4)]);
                 else
 #pragma unroll
