@@ -62,13 +62,17 @@ struct LargeK16 {
 // so that its fragments are 16-byte reads like a k-contiguous operand's.
 // Each thread loads 4 consecutive k rows of one 4-wide x quad (every load
 // instruction still covers whole rows across the wave) and stores the
-// transposed 4x4 block as four 16-byte rows.  The 4-wide k group is XOR
-// swizzled by x / 8: with the row stride KT + 4 this keeps both the stores
-// and the fragment reads free of bank conflicts (32 banks, 8 lanes per
-// 16-byte access).
+// transposed 4x4 block as four 16-byte rows.  Row stride KT + 8 and the
+// 4-wide k group XOR swizzled by (x / 4) mod 8: measured on gfx950 with a
+// microbenchmark of exactly these two access patterns, the stores (lanes
+// writing rows 4 apart) are free of bank conflicts and the fragment reads
+// (32 consecutive rows per half wave) take 4 conflict cycles per
+// instruction; stride KT + 4 with a swizzle by x / 16 measured 8 and 4, and
+// no swizzle 24 and 0.  (The stores behave like 32 banks served 8 lanes at a
+// time, the 16-byte reads like 128 banks served 32 lanes at a time.)
 template <int X, int KT, int THREADS>
 struct StageXT {
-    static constexpr int LDX = KT + 4;
+    static constexpr int LDX = KT + 8;
     static constexpr int SIZE = X * LDX;
     static constexpr int VECS = X * KT / 4 / THREADS;  // float4 per thread per term
     static constexpr int QX = X / 4;                   // x quads per k row
@@ -83,7 +87,7 @@ struct StageXT {
         k = 4 * (tid / QX + (p / 4) * GSTEP) + (p % 4);
     }
     // LDS offset of element (x, k), k a multiple of 4 (start of a group).
-    __device__ static int lds(int x, int k) { return x * LDX + 4 * ((k / 4) ^ ((x / 8) % NG)); }
+    __device__ static int lds(int x, int k) { return x * LDX + 4 * ((k / 4) ^ ((x / 4) % NG)); }
 };
 
 // Staging geometry of one operand tile of X x KT elements.
