@@ -9,20 +9,30 @@ the machine balance (eqs. constrain_glb, constrain_sha_bdw).  The same form
 is used here with the gfx950 resources the kernels actually use:
 
   flop   MFMA flops                    / (CUs * MFMA flop/clk/CU * clock)
+  valu   operand-staging VALU ops      / (CUs * 64 lane-ops/clk * clock)
   lds    LDS bytes written + read      / (CUs * 128 B/clk * clock)
   l2     L2 -> CU operand bytes        / (CUs * L2 B/clk/CU * clock)
   hbm    algorithmic HBM bytes         / HBM bandwidth
 
 per launch (one race-free batch of products of one variant), with the
-counts of one workgroup tile:
+counts of one workgroup tile.  The staging VALU work is added to the MFMA
+time rather than overlapped with it: each wave issues its sums in order with
+its MFMAs and meets a barrier every k-tile, and measured kernels lose about
+the VALU/MFMA ratio (fp32 W > 1 kernels a few per cent; 16-bit one-level
+launches more than the flops they save):
   operand bytes per k-tile   (W_A * MT + W_B * NT) * KT * b_in        (l2)
   LDS bytes per k-tile       (MT + NT) * KT * b_lds * planes           (stores)
                              + waves * (WM + WN) * KT * b_lds * planes (fragment reads)
   C bytes per tile           2 * 4 * W_C * MT * NT                     (epilogue)
+  staging ops per k-tile     per element of each operand tile: fp32 one
+                             multiply-add per term; 16-bit one pass-through
+                             (single term) or a convert and an FMA per term
+                             plus half a packed rounding; bf16x3 adds the
+                             hi/lo split
 and a wave-quantisation factor ceil(W / S) / (W / S) for W workgroups on S
 slots (the paper's inter-kernel parallelism argument for small problems).
-A launch costs the maximum of its resource times, times that factor, plus a
-fixed launch overhead.  The constants below are public MI355X figures, the
+A launch costs max(T_flop + T_valu, T_lds, T_l2, T_hbm) times that factor,
+plus a fixed launch overhead.  The constants below are public MI355X figures, the
 L2 and LDS widths are per-CU figures of the CDNA generation, and the clock
 is the one measured under the fp32 GEMM (GRBM_GUI_ACTIVE).
 """
@@ -31,9 +41,10 @@ import math
 from . import _binding as B
 
 CUS = 256
-CLOCK_HZ = 2.31e9            # measured under load (nominal 2.4 GHz)
+CLOCK_HZ = 2.38e9            # measured under load (GRBM_GUI_ACTIVE per XCD)
 MFMA_FLOP_PER_CLK_CU = {"f32": 256.0, "16bit": 4096.0}
 LDS_B_PER_CLK_CU = 128.0
+VALU_OPS_PER_CLK_CU = 64.0   # 4 SIMDs x 16 lanes
 L2_B_PER_CLK_CU = 64.0
 HBM_B_PER_S = 8.0e12
 LAUNCH_S = 6e-6
@@ -92,17 +103,29 @@ def predict(m, n, k, levels, kind="f32"):
         flops = 2.0 * mt * nt * kt * ktiles * tiles * mfma_mult
         lds = ((mt + nt) * kt * b_lds * planes + waves * (wm + wn) * kt * b_lds * planes) * ktiles * tiles
         l2 = (wa * mt + wb * nt) * kt * b_in * ktiles * tiles
+
+        def staging(w):  # VALU lane-ops per element of one operand tile
+            if kind == "f32":
+                return float(w)
+            if kind == "x3":
+                return 2.0 * w + 3.0
+            return 0.125 if w == 1 else 2.0 * w + 0.5
+        valu = (mt * staging(wa) + nt * staging(wb)) * kt * ktiles * tiles
         hbm = batch * (b_in * (wa * sm * sk + wb * sk * sn) + 8 * wc * sm * sn)
         t = {
             "flop": flops / (CUS * MFMA_FLOP_PER_CLK_CU[rate_kind] * CLOCK_HZ),
+            "valu": valu / (CUS * VALU_OPS_PER_CLK_CU * CLOCK_HZ),
             "lds": lds / (CUS * LDS_B_PER_CLK_CU * CLOCK_HZ),
             "l2": l2 / (CUS * L2_B_PER_CLK_CU * CLOCK_HZ),
             "hbm": hbm / HBM_B_PER_S,
         }
         slots = CUS * slots_per_cu
         quant = math.ceil(tiles / slots) / (tiles / slots)
-        bound = max(t, key=t.get)
-        secs = t[bound] * quant + LAUNCH_S
+        limits = {"compute": t["flop"] + t["valu"], "lds": t["lds"], "l2": t["l2"], "hbm": t["hbm"]}
+        bound = max(limits, key=limits.get)
+        secs = limits[bound] * quant + LAUNCH_S
+        if bound == "compute":
+            bound = "flop" if t["flop"] >= t["valu"] else "valu"
         total += secs
         launches.append({"variant": (wa, wb, wc), "batch": batch, "tile": (mt, nt, kt),
                          "workgroups": tiles, "bound": bound, "seconds": secs,
