@@ -550,6 +550,42 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
         ccols[o] = P.c[o].cols;
         cfirst[o] = P.c[o].first;
     }
+    // Interior tiles (every output block covers the whole tile): no
+    // per-element guards, so each block's 16 reads of C per output are issued
+    // together before its stores.
+    bool c_full = true;
+#pragma unroll
+    for (int o = 0; o < WC; ++o)
+        c_full = c_full && row0 + C::MT <= crows[o] && col0 + C::NT <= ccols[o];
+    if (c_full) {
+#pragma unroll
+        for (int i = 0; i < C::BM; ++i)
+#pragma unroll
+            for (int j = 0; j < C::BN; ++j) {
+                const int cj = col0 + wn * C::WN + j * 32 + l32;
+                const int ci0 = row0 + wm * C::WM + i * 32 + 4 * h;
+#pragma unroll
+                for (int o = 0; o < WC; ++o) {
+                    float *pc = Cm + coff[o] + (int64_t)ci0 * ldc + cj;
+                    const bool read = !(cfirst[o] && beta == 0.f);
+                    const float cb = cfirst[o] ? beta : 1.f;
+                    if (read) {
+                        float cv[16];
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) cv[r] = pc[(int64_t)(8 * (r >> 2) + (r & 3)) * ldc];
+#pragma unroll
+                        for (int r = 0; r < 16; ++r)
+                            pc[(int64_t)(8 * (r >> 2) + (r & 3)) * ldc] = cb * cv[r] + g[o] * acc[i][j][r];
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 16; ++r)
+                            pc[(int64_t)(8 * (r >> 2) + (r & 3)) * ldc] = g[o] * acc[i][j][r];
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < C::BM; ++i)
 #pragma unroll
