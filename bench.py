@@ -84,6 +84,16 @@ def cpu_baseline(A, B, C, target_s):
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "strassen_f32_16384_traffic.md")
 
 
+def kernel_source_text(path):
+    """The code of a C++ source without comments or whitespace: the part of
+    a kernel source that can change the kernel."""
+    import re
+    src = open(path).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return "".join(src.split())
+
+
 def measured_traffic(kernel, workgroups):
     """HBM bytes per launch of `kernel` launched with `workgroups` workgroups,
     from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when
@@ -95,13 +105,14 @@ def measured_traffic(kernel, workgroups):
         text = open(TRAFFIC_SUMMARY).read()
     except OSError:
         return None
-    m = re.search(r"kernel-source-sha256: ([0-9a-f]{64}) \(sha256 over (.*?), concatenated\)", text)
+    m = re.search(r"kernel-source-sha256: ([0-9a-f]{64}) \(sha256 over (.*?), concatenated, "
+                  r"comments and whitespace removed\)", text)
     if not m:
         return None
     h = hashlib.sha256()
     for f in m.group(2).split(", "):
         try:
-            h.update(open(os.path.join(ROOT, f), "rb").read())
+            h.update(kernel_source_text(os.path.join(ROOT, f)).encode())
         except OSError:
             return None
     if h.hexdigest() != m.group(1):

@@ -16,10 +16,12 @@
 // W_A, W_B, W_C (Register Optimization section) are template parameters, so
 // a variant with one term per operand carries no extra loads or adds.
 //
-// Operand layouts.  Each operand is staged in the direction it is contiguous
+// Operand layouts.  Each operand is loaded in the direction it is contiguous
 // in memory, so global loads are 16-byte vectors and LDS stores are 16-byte:
 //   KC  (k contiguous: A as stored, or B stored transposed)  -> LDS [x][k]
-//   XC  (m/n contiguous: B as stored, or A stored transposed) -> LDS [k][x]
+//   XC  (m/n contiguous: B as stored, or A stored transposed) -> LDS [k][x],
+//       or [x][k] through 4x4 register transposes (StageXT) in variants with
+//       three or more operand terms
 // where x is the operand's m (A) or n (B) index.  Element (x, k) of a block
 // lives at off + x*ld + k (KC) or off + k*ld + x (XC).
 #pragma once
@@ -35,8 +37,9 @@ namespace strassen {
 namespace f32k {
 
 // Tile shapes.  Small: 128x128x32, 4 waves of 64x64, two workgroups per CU.
-// Large: 256x256x16, 8 waves of 128x64, one workgroup per CU; half the L2
-// traffic per flop of Small, for variants with several terms per operand.
+// Large: 256x256x32, 8 waves of 128x64, one workgroup per CU; half the L2
+// traffic per flop of Small.  LargeK16: the same with a 16-deep k-tile, for
+// variants whose staging registers do not fit twice as deep.
 struct Small {
     static constexpr int MT = 128, NT = 128, KT = 32;
     static constexpr int WAVES_M = 2, WAVES_N = 2;

@@ -4,7 +4,8 @@
 //
 // Three operand modes share one template:
 //   * bf16 operands  -> signed sums in fp32, rounded once to bf16 (nearest
-//                       even) on the way into LDS, bf16 MFMA;
+//                       even) on the way into LDS, bf16 MFMA (a single-term
+//                       operand is copied without arithmetic);
 //   * fp16 operands  -> the same with fp16;
 //   * fp32 operands, compensated ("bf16x3") -> each fp32 operand sum x is split
 //                       into hi = bf16(x) and lo = bf16(x - hi); LDS holds the
@@ -45,7 +46,7 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 // KT + 8 (the eight rows of one 16-byte read cycle land in distinct bank
 // groups), paired tiles KT + 4 (32 consecutive columns fall on 32 distinct
 // even banks for the 8-byte reads, and the 4-byte staging stores of one wave
-// on 64 distinct banks).
+// on 64 distinct banks); SQ_LDS_BANK_CONFLICT measures 0 for these kernels.
 template <int MT_, int NT_, int KT_, int WAVES_M_, int WAVES_N_, int GROUP_>
 struct Cfg {
     static constexpr int MT = MT_, NT = NT_, KT = KT_;
