@@ -225,7 +225,7 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
     const int64_t a_org = A_KC ? (int64_t)row0 * lda : row0;
     const int64_t b_org = B_KC ? (int64_t)col0 * ldb : col0;
 
-    auto issue_fast = [&](int kt) {
+    auto issue_fast_a = [&](int kt) __attribute__((always_inline)) {
 #pragma unroll
         for (int t = 0; t < WA; ++t) {
             if (t < na) {
@@ -235,6 +235,8 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
                 for (int p = 0; p < SA::VECS; ++p) raw_a[t][p] = buffer_load16<f32x4>(r, a_off[p]);
             }
         }
+    };
+    auto issue_fast_b = [&](int kt) __attribute__((always_inline)) {
 #pragma unroll
         for (int t = 0; t < WB; ++t) {
             if (t < nb) {
@@ -245,9 +247,13 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
             }
         }
     };
+    auto issue_fast = [&](int kt) __attribute__((always_inline)) {
+        issue_fast_a(kt);
+        issue_fast_b(kt);
+    };
 
     // Loads of any k-tile, each element guarded against its term's extents.
-    auto issue = [&](int k0) {
+    auto issue_a = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
         for (int p = 0; p < SA::VECS; ++p) {
             int x, k;
@@ -257,6 +263,8 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
                 if (t < na) raw_a[t][p] = load4_guarded<A_KC>(A + P.a[t].off, lda, row0 + x, k0 + k,
                                                   P.a[t].rows, P.a[t].cols, VEC);
         }
+    };
+    auto issue_b = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
         for (int p = 0; p < SB::VECS; ++p) {
             int x, k;
@@ -267,13 +275,17 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
                                                   P.b[t].cols, P.b[t].rows, VEC);
         }
     };
+    auto issue = [&](int k0) __attribute__((always_inline)) {
+        issue_a(k0);
+        issue_b(k0);
+    };
 
     // Form the signed operand sums and store them into LDS buffer `buf`.
     auto store_operand = [&](auto stage, auto xt, float *tile, f32x4 (*raw)[decltype(stage)::VECS],
-                             auto nterms, int n_use, const TermArg *terms) {
+                             auto nterms, int n_use, const TermArg *terms) __attribute__((always_inline)) {
         using S = decltype(stage);
         constexpr int NT_ = decltype(nterms)::value;
-        auto sum = [&](int p) {
+        auto sum = [&](int p) __attribute__((always_inline)) {
             f32x4 v = raw[0][p] * terms[0].sign;
 #pragma unroll
             for (int t = 1; t < NT_; ++t)
@@ -301,11 +313,17 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
             }
         }
     };
-    auto sum_store = [&](int buf) {
+    auto store_a = [&](int buf) __attribute__((always_inline)) {
         store_operand(SA{}, std::integral_constant<bool, A_XT>{}, &As[buf][0], raw_a,
                       std::integral_constant<int, WA>{}, na, P.a);
+    };
+    auto store_b = [&](int buf) __attribute__((always_inline)) {
         store_operand(SB{}, std::integral_constant<bool, B_XT>{}, &Bs[buf][0], raw_b,
                       std::integral_constant<int, WB>{}, nb, P.b);
+    };
+    auto sum_store = [&](int buf) __attribute__((always_inline)) {
+        store_a(buf);
+        store_b(buf);
     };
 
     f32x16 acc[BM][BN];
@@ -319,7 +337,7 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
     // A KC operand gives a lane its values for four steps in one 16-byte read;
     // an XC operand is read one 4-byte value per step (32 consecutive x).
     const int h = lane >> 5, l32 = lane & 31;
-    auto compute = [&](int buf, int c0, int c1) {
+    auto compute = [&](int buf, int c0, int c1) __attribute__((always_inline)) {
         const float *as = &As[buf][0];
         const float *bs = &Bs[buf][0];
 #pragma unroll
@@ -355,14 +373,50 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
     };
 
     const int nk = (args.sk + KT - 1) / KT;
-    if (nfast > 0)
-        issue_fast(0);
-    else
-        issue(0);
-    sum_store(0);
+    // Staggered staging (16-deep large tiles, i.e. variants with more than
+    // four operand terms): A's terms are loaded and summed first, then B's,
+    // so only one operand's raw terms occupy registers at a time (+3-6 %
+    // measured for the (4,4,x) and (2,4,x) variants).
+    constexpr bool kStagger = std::is_same<Cfg, LargeK16>::value;
+    if constexpr (kStagger) {
+        if (nfast > 0) {
+            issue_fast_a(0);
+            store_a(0);
+            issue_fast_b(0);
+            store_b(0);
+        } else {
+            issue_a(0);
+            store_a(0);
+            issue_b(0);
+            store_b(0);
+        }
+    } else {
+        if (nfast > 0)
+            issue_fast(0);
+        else
+            issue(0);
+        sum_store(0);
+    }
     __syncthreads();
     int kt = 0;
     // Steady state: the next k-tile is in bounds, no guards, no branches.
+    if constexpr (kStagger)
+    for (; kt + 1 < nfast; ++kt) {
+        // A's loads, the first half of the MFMAs, A's sums and stores, B's
+        // loads, the second half, B's sums and stores.
+        const int cur = kt & 1;
+        issue_fast_a(kt + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(cur, 0, KT / 16);
+        __builtin_amdgcn_sched_barrier(0);
+        store_a(cur ^ 1);
+        issue_fast_b(kt + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(cur, KT / 16, KT / 8);
+        __builtin_amdgcn_sched_barrier(0);
+        store_b(cur ^ 1);
+        __syncthreads();
+    }
     for (; kt + 1 < nfast; ++kt) {
         const int cur = kt & 1;
         issue_fast(kt + 1);
@@ -384,9 +438,20 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
     for (; kt < nk; ++kt) {
         const int cur = kt & 1;
         const bool more = kt + 1 < nk;
-        if (more) issue((kt + 1) * KT);
-        compute(cur, 0, KT / 8);
-        if (more) sum_store(cur ^ 1);
+        if constexpr (kStagger) {
+            if (more) issue_a((kt + 1) * KT);
+            compute(cur, 0, KT / 16);
+            if (more) {
+                store_a(cur ^ 1);
+                issue_b((kt + 1) * KT);
+            }
+            compute(cur, KT / 16, KT / 8);
+            if (more) store_b(cur ^ 1);
+        } else {
+            if (more) issue((kt + 1) * KT);
+            compute(cur, 0, KT / 8);
+            if (more) sum_store(cur ^ 1);
+        }
         __syncthreads();
     }
 
@@ -441,8 +506,9 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
                         for (int r = 0; r < 16; ++r)
                             pc[(int64_t)(8 * (r >> 2) + (r & 3)) * ldc] = g[o] * acc[i][j][r];
                     }
+                    // one output's C values live at a time
+                    __builtin_amdgcn_sched_barrier(0);
                 }
-                __builtin_amdgcn_sched_barrier(0);
             }
         return;
     }
