@@ -112,7 +112,7 @@ struct X3Ops {
 // Staging geometry of one operand (X = MT or NT rows of the [x][k] tile).
 // direct: units of one x row and NV consecutive k; paired: units of two
 // consecutive k rows and NV consecutive x.
-template <class C, class Ops, int X, bool DIRECT>
+template <class C, class Ops, int X, bool DIRECT, bool ONE_TERM>
 struct Stage {
     static constexpr int NV = Ops::NV;
     static constexpr int LDX = DIRECT ? C::KT + 8 : C::KT + 4;
@@ -121,6 +121,17 @@ struct Stage {
     static constexpr int VECS = UNITS / C::THREADS;  // units per thread per term
     static constexpr int LOADS = DIRECT ? 1 : 2;     // global vectors per unit
     static_assert(VECS * C::THREADS == UNITS, "tile split");
+    // Single-term paired 16-bit tiles 256 wide: consecutive lanes take
+    // consecutive x units of one k row pair, so one load instruction covers
+    // two rows (8 cache lines instead of 32; the 32-row spread filled the
+    // texture-address queue of these buffer-load kernels for 13 % of their
+    // cycles).  The staging stores of one wave then hit rows 8 apart; the
+    // 4-element groups of each LDS row are XOR-swizzled with (x / 32) mod 8,
+    // which keeps both those stores and the fragment reads free of bank
+    // conflicts (64 banks of 4 bytes, checked for KT = 32 and 64).  Summed
+    // operands keep the k-major unit order: there the swizzled fragment
+    // addresses cost registers the staging needs.
+    static constexpr bool SWZ = !DIRECT && NV == 8 && X >= 256 && ONE_TERM;
 
     // Unit p of thread tid: first (x, k) it covers.
     __device__ static void coords(int tid, int p, int &x, int &k) {
@@ -129,11 +140,22 @@ struct Stage {
             constexpr int PER_ROW = C::KT / NV;
             x = u / PER_ROW;
             k = (u % PER_ROW) * NV;
+        } else if (SWZ) {
+            constexpr int PER_ROW = X / NV;
+            x = (u % PER_ROW) * NV;
+            k = 2 * (u / PER_ROW);
         } else {
             constexpr int PAIRS = C::KT / 2;
             k = 2 * (u % PAIRS);
             x = (u / PAIRS) * NV;
         }
+    }
+    // Offset of element (x, k) in the tile (paired layouts: k even or a
+    // multiple of 4).  Rows x .. x + 7 of one staging unit (x a multiple of
+    // 8) share the swizzle, so their offsets are at(x, k) + e * LDX.
+    __device__ static int at(int x, int k) {
+        if (SWZ) return x * LDX + 4 * ((k >> 2) ^ ((x >> 5) & 7)) + (k & 3);
+        return x * LDX + k;
     }
 };
 
@@ -167,8 +189,8 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
     using V = typename Ops::Vec;
     constexpr int NV = Ops::NV;
     constexpr int NPLANES = Ops::kX3 ? 2 : 1;  // hi (and lo) tiles
-    using SA = Stage<C, Ops, C::MT, A_KC>;
-    using SB = Stage<C, Ops, C::NT, B_KC>;
+    using SA = Stage<C, Ops, C::MT, A_KC, WA == 1>;
+    using SB = Stage<C, Ops, C::NT, B_KC, WB == 1>;
     __shared__ __attribute__((aligned(16))) unsigned short As[2][NPLANES][SA::SIZE];
     __shared__ __attribute__((aligned(16))) unsigned short Bs[2][NPLANES][SB::SIZE];
 
@@ -374,18 +396,20 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
                     }
                 }
             } else if constexpr (kCopyA) {
+                const int base = SA::at(x, k);
 #pragma unroll
                 for (int e = 0; e < NV; ++e)
-                    *reinterpret_cast<unsigned *>(&As[buf][0][(x + e) * SA::LDX + k]) =
+                    *reinterpret_cast<unsigned *>(&As[buf][0][base + e * SA::LDX]) =
                         pair_words(raw_a[0][p][0], raw_a[0][p][1], e);
             } else {
                 // paired: k rows k, k+1 of NV consecutive x
+                const int base = SA::at(x, k);
 #pragma unroll
                 for (int e = 0; e < NV; ++e) {
                     const float s0 = sum_elem(raw_a, P.a, sa0, std::integral_constant<int, WA>{}, p, 0, e);
                     const float s1 = sum_elem(raw_a, P.a, sa0, std::integral_constant<int, WA>{}, p, 1, e);
                     const unsigned hw = Ops::pack2(s0, s1);
-                    const int off = (x + e) * SA::LDX + k;
+                    const int off = base + e * SA::LDX;
                     *reinterpret_cast<unsigned *>(&As[buf][0][off]) = hw;
                     if constexpr (Ops::kX3) {
                         const float r0 = s0 - __uint_as_float(hw << 16);
@@ -427,17 +451,19 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
                     }
                 }
             } else if constexpr (kCopyB) {
+                const int base = SB::at(x, k);
 #pragma unroll
                 for (int e = 0; e < NV; ++e)
-                    *reinterpret_cast<unsigned *>(&Bs[buf][0][(x + e) * SB::LDX + k]) =
+                    *reinterpret_cast<unsigned *>(&Bs[buf][0][base + e * SB::LDX]) =
                         pair_words(raw_b[0][p][0], raw_b[0][p][1], e);
             } else {
+                const int base = SB::at(x, k);
 #pragma unroll
                 for (int e = 0; e < NV; ++e) {
                     const float s0 = sum_elem(raw_b, P.b, sb0, std::integral_constant<int, WB>{}, p, 0, e);
                     const float s1 = sum_elem(raw_b, P.b, sb0, std::integral_constant<int, WB>{}, p, 1, e);
                     const unsigned hw = Ops::pack2(s0, s1);
-                    const int off = (x + e) * SB::LDX + k;
+                    const int off = base + e * SB::LDX;
                     *reinterpret_cast<unsigned *>(&Bs[buf][0][off]) = hw;
                     if constexpr (Ops::kX3) {
                         const float r0 = s0 - __uint_as_float(hw << 16);
@@ -469,11 +495,11 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
     // Eight consecutive k of tile row x: one 16-byte read (direct stride is a
     // multiple of 16 bytes) or two 8-byte reads (paired stride is a multiple
     // of 8 bytes).
-    auto frag = [&](const unsigned short *tile, int ldx, bool direct, int x, int k) __attribute__((always_inline)) -> u32x4 {
-        const unsigned short *p = tile + x * ldx + k;
-        if (direct) return *reinterpret_cast<const u32x4 *>(p);
-        const u32x2 lo2 = *reinterpret_cast<const u32x2 *>(p);
-        const u32x2 hi2 = *reinterpret_cast<const u32x2 *>(p + 4);
+    auto frag = [&](const unsigned short *tile, auto stage, int x, int k) __attribute__((always_inline)) -> u32x4 {
+        using S = decltype(stage);
+        if constexpr (S::LOADS == 1) return *reinterpret_cast<const u32x4 *>(tile + x * S::LDX + k);
+        const u32x2 lo2 = *reinterpret_cast<const u32x2 *>(tile + S::at(x, k));
+        const u32x2 hi2 = *reinterpret_cast<const u32x2 *>(tile + S::at(x, k + 4));
         return u32x4{lo2.x, lo2.y, hi2.x, hi2.y};
     };
     auto compute = [&](int buf) __attribute__((always_inline)) {
@@ -484,12 +510,10 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
             for (int q = 0; q < NPLANES; ++q) {
 #pragma unroll
                 for (int i = 0; i < C::BM; ++i)
-                    af[q][i] = frag(&As[buf][q][0], SA::LDX, A_KC, wm * C::WM + i * 32 + l32,
-                                    16 * s + 8 * h);
+                    af[q][i] = frag(&As[buf][q][0], SA{}, wm * C::WM + i * 32 + l32, 16 * s + 8 * h);
 #pragma unroll
                 for (int j = 0; j < C::BN; ++j)
-                    bf[q][j] = frag(&Bs[buf][q][0], SB::LDX, B_KC, wn * C::WN + j * 32 + l32,
-                                    16 * s + 8 * h);
+                    bf[q][j] = frag(&Bs[buf][q][0], SB{}, wn * C::WN + j * 32 + l32, 16 * s + 8 * h);
             }
 #pragma unroll
             for (int i = 0; i < C::BM; ++i)
