@@ -268,16 +268,23 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
 
     // In-bounds k-tiles [0, nfast): unguarded loads from a uniform per-term
     // base (advanced one k-tile per step) plus a per-thread 32-bit byte
-    // offset that does not change along k.  Single-term operands use buffer
-    // loads (measured faster); with more terms plain global loads measured
-    // faster here.
-    constexpr bool kBufferLoads = WA + WB <= 2;
-    constexpr uint64_t kOffLimit = 1ull << 32;
-    const bool off32 = (uint64_t)(A_KC ? C::MT : C::KT) * (uint64_t)lda * sizeof(In) < kOffLimit &&
-                       (uint64_t)(B_KC ? C::NT : C::KT) * (uint64_t)ldb * sizeof(In) < kOffLimit;
+    // offset that does not change along k.
     // (The compensated mode with four terms on both operands has no
     // registers to spare for the offsets and keeps the guarded loop.)
     constexpr bool kFastLoop = !(Ops::kX3 && WA + WB >= 8);
+    // The compensated mode with at most four terms on 256x256 tiles loads
+    // two k-tiles ahead (a second set of staging registers): its 16-deep
+    // k-tile is ~1500 MFMA cycles per SIMD, shorter than the latency of the
+    // next tile's loads.  Measured +4-6 % for (1,1,1), (2,1,2), (2,2,1) and
+    // (2,2,2); for bf16/fp16 operands (64-deep k-tiles) it measured 1-3 %
+    // slower and is not used.
+    constexpr bool kDeep = kFastLoop && Ops::kX3 && WA + WB <= 4 && C::MT == 256;
+    // Buffer loads for single-term operands and the two-ahead loop (measured
+    // faster there); otherwise plain global loads measured faster.
+    constexpr bool kBufferLoads = WA + WB <= 2 || kDeep;
+    constexpr uint64_t kOffLimit = 1ull << 32;
+    const bool off32 = (uint64_t)(A_KC ? C::MT : C::KT) * (uint64_t)lda * sizeof(In) < kOffLimit &&
+                       (uint64_t)(B_KC ? C::NT : C::KT) * (uint64_t)ldb * sizeof(In) < kOffLimit;
     const int nfast = (kFastLoop && vec && a_x_full && b_x_full && off32)
                           ? (a_k < b_k ? a_k : b_k) / C::KT : 0;
     uint32_t a_off[SA::VECS][SA::LOADS], b_off[SB::VECS][SB::LOADS];
@@ -325,12 +332,13 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
             }
         }
     };
-    auto stage_load_fast = [&](int kt) __attribute__((always_inline)) {
+    auto stage_load_fast_into = [&](int kt, auto &ra, auto &rb) __attribute__((always_inline)) {
         if constexpr (kFastLoop) {
-            load_fast(raw_a, A, P.a, SA{}, std::integral_constant<int, WA>{}, a_off, a_org, a_step, kt);
-            load_fast(raw_b, B, P.b, SB{}, std::integral_constant<int, WB>{}, b_off, b_org, b_step, kt);
+            load_fast(ra, A, P.a, SA{}, std::integral_constant<int, WA>{}, a_off, a_org, a_step, kt);
+            load_fast(rb, B, P.b, SB{}, std::integral_constant<int, WB>{}, b_off, b_org, b_step, kt);
         }
     };
+    auto stage_load_fast = [&](int kt) __attribute__((always_inline)) { stage_load_fast_into(kt, raw_a, raw_b); };
 
     // Sign of the first term of each operand: factored out of the operand
     // sum and applied in the epilogue instead (signs are +-1 and rounding to
@@ -360,22 +368,22 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
         return __builtin_amdgcn_perm(r1[e >> 1], r0[e >> 1], (e & 1) ? 0x07060302u : 0x05040100u);
     };
 
-    // Signed sums rounded to the MFMA type (split into hi/lo for the
-    // compensated mode), stored into LDS buffer `buf`.
-    auto stage_store = [&](int buf) __attribute__((always_inline)) {
+    // Signed sums of the raw terms ra / rb rounded to the MFMA type (split
+    // into hi/lo for the compensated mode), stored into LDS buffer `buf`.
+    auto stage_store_from = [&](int buf, auto &ra, auto &rb) __attribute__((always_inline)) {
         // ---- A ----
 #pragma unroll
         for (int p = 0; p < SA::VECS; ++p) {
             int x, k;
             SA::coords(tid, p, x, k);
             if constexpr (A_KC && kCopyA) {
-                *reinterpret_cast<V *>(&As[buf][0][x * SA::LDX + k]) = raw_a[0][p][0];
+                *reinterpret_cast<V *>(&As[buf][0][x * SA::LDX + k]) = ra[0][p][0];
             } else if constexpr (A_KC) {
                 // direct: NV consecutive k of row x
                 unsigned short hi[NV], lo[NV];
 #pragma unroll
                 for (int e = 0; e < NV; ++e) {
-                    const float s = sum_elem(raw_a, P.a, sa0, std::integral_constant<int, WA>{}, p, 0, e);
+                    const float s = sum_elem(ra, P.a, sa0, std::integral_constant<int, WA>{}, p, 0, e);
                     hi[e] = Ops::from_f32(s);
                     if constexpr (Ops::kX3) lo[e] = Ops::from_f32(s - Ops::bf16_to_f32(hi[e]));
                 }
@@ -400,14 +408,14 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
 #pragma unroll
                 for (int e = 0; e < NV; ++e)
                     *reinterpret_cast<unsigned *>(&As[buf][0][base + e * SA::LDX]) =
-                        pair_words(raw_a[0][p][0], raw_a[0][p][1], e);
+                        pair_words(ra[0][p][0], ra[0][p][1], e);
             } else {
                 // paired: k rows k, k+1 of NV consecutive x
                 const int base = SA::at(x, k);
 #pragma unroll
                 for (int e = 0; e < NV; ++e) {
-                    const float s0 = sum_elem(raw_a, P.a, sa0, std::integral_constant<int, WA>{}, p, 0, e);
-                    const float s1 = sum_elem(raw_a, P.a, sa0, std::integral_constant<int, WA>{}, p, 1, e);
+                    const float s0 = sum_elem(ra, P.a, sa0, std::integral_constant<int, WA>{}, p, 0, e);
+                    const float s1 = sum_elem(ra, P.a, sa0, std::integral_constant<int, WA>{}, p, 1, e);
                     const unsigned hw = Ops::pack2(s0, s1);
                     const int off = base + e * SA::LDX;
                     *reinterpret_cast<unsigned *>(&As[buf][0][off]) = hw;
@@ -425,12 +433,12 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
             int x, k;
             SB::coords(tid, p, x, k);
             if constexpr (B_KC && kCopyB) {
-                *reinterpret_cast<V *>(&Bs[buf][0][x * SB::LDX + k]) = raw_b[0][p][0];
+                *reinterpret_cast<V *>(&Bs[buf][0][x * SB::LDX + k]) = rb[0][p][0];
             } else if constexpr (B_KC) {
                 unsigned short hi[NV], lo[NV];
 #pragma unroll
                 for (int e = 0; e < NV; ++e) {
-                    const float s = sum_elem(raw_b, P.b, sb0, std::integral_constant<int, WB>{}, p, 0, e);
+                    const float s = sum_elem(rb, P.b, sb0, std::integral_constant<int, WB>{}, p, 0, e);
                     hi[e] = Ops::from_f32(s);
                     if constexpr (Ops::kX3) lo[e] = Ops::from_f32(s - Ops::bf16_to_f32(hi[e]));
                 }
@@ -455,13 +463,13 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
 #pragma unroll
                 for (int e = 0; e < NV; ++e)
                     *reinterpret_cast<unsigned *>(&Bs[buf][0][base + e * SB::LDX]) =
-                        pair_words(raw_b[0][p][0], raw_b[0][p][1], e);
+                        pair_words(rb[0][p][0], rb[0][p][1], e);
             } else {
                 const int base = SB::at(x, k);
 #pragma unroll
                 for (int e = 0; e < NV; ++e) {
-                    const float s0 = sum_elem(raw_b, P.b, sb0, std::integral_constant<int, WB>{}, p, 0, e);
-                    const float s1 = sum_elem(raw_b, P.b, sb0, std::integral_constant<int, WB>{}, p, 1, e);
+                    const float s0 = sum_elem(rb, P.b, sb0, std::integral_constant<int, WB>{}, p, 0, e);
+                    const float s1 = sum_elem(rb, P.b, sb0, std::integral_constant<int, WB>{}, p, 1, e);
                     const unsigned hw = Ops::pack2(s0, s1);
                     const int off = base + e * SB::LDX;
                     *reinterpret_cast<unsigned *>(&Bs[buf][0][off]) = hw;
@@ -474,6 +482,8 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
             }
         }
     };
+
+    auto stage_store = [&](int buf) __attribute__((always_inline)) { stage_store_from(buf, raw_a, raw_b); };
 
     f32x16 acc[C::BM][C::BN];
 #pragma unroll
@@ -529,13 +539,43 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
     };
 
     const int nk = (args.sk + C::KT - 1) / C::KT;
-    if (nfast > 0)
-        stage_load_fast(0);
-    else
-        stage_load(0);
-    stage_store(0);
-    __syncthreads();
     int kt = 0;
+    if (kDeep && nfast >= 3) {
+        // Two k-tiles per trip, the register sets alternating: tile kt is in
+        // LDS buffer 0 and tile kt + 1 in raw_a/raw_b at the top of a trip.
+        // The loop ends with tile kt in buffer 1; the loops below go on.
+        V q_a[WA][SA::VECS][SA::LOADS];
+        V q_b[WB][SB::VECS][SB::LOADS];
+        stage_load_fast(0);
+        stage_store(0);
+        stage_load_fast(1);
+        __syncthreads();
+        for (; kt + 3 < nfast; kt += 2) {
+            stage_load_fast_into(kt + 2, q_a, q_b);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(0);
+            __builtin_amdgcn_sched_barrier(0);
+            stage_store_from(1, raw_a, raw_b);
+            __syncthreads();
+            stage_load_fast_into(kt + 3, raw_a, raw_b);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(1);
+            __builtin_amdgcn_sched_barrier(0);
+            stage_store_from(0, q_a, q_b);
+            __syncthreads();
+        }
+        compute(0);
+        stage_store_from(1, raw_a, raw_b);
+        __syncthreads();
+        kt += 1;
+    } else {
+        if (nfast > 0)
+            stage_load_fast(0);
+        else
+            stage_load(0);
+        stage_store(0);
+        __syncthreads();
+    }
     // Steady state: the next k-tile is in bounds.  The scheduling barriers
     // keep its loads ahead of the MFMA block and the sums behind it, so the
     // load latency is covered by a whole k-tile of MFMAs.
