@@ -10,7 +10,8 @@ is used here with the gfx950 resources the kernels actually use:
 
   flop   MFMA flops                    / (CUs * MFMA flop/clk/CU * clock)
   valu   operand-staging VALU ops      / (CUs * 64 lane-ops/clk * clock)
-  lds    LDS bytes written + read      / (CUs * 128 B/clk * clock)
+  lds    LDS bytes written / (CUs * 128 B/clk * clock)
+         + LDS bytes read  / (CUs * 256 B/clk * clock)
   l2     L2 -> CU operand bytes        / (CUs * L2 B/clk/CU * clock)
   hbm    algorithmic HBM bytes         / HBM bandwidth
 
@@ -32,18 +33,26 @@ launches more than the flops they save):
 and a wave-quantisation factor ceil(W / S) / (W / S) for W workgroups on S
 slots (the paper's inter-kernel parallelism argument for small problems).
 A launch costs max(T_flop + T_valu, T_lds, T_l2, T_hbm) times that factor,
-plus a fixed launch overhead.  The constants below are public MI355X figures, the
-L2 and LDS widths are per-CU figures of the CDNA generation, and the clock
-is the one measured under the fp32 GEMM (GRBM_GUI_ACTIVE).
+plus a fixed launch overhead.  The constants below are public MI355X figures
+or measured on it: the LDS widths with a microbenchmark (16-byte reads 256
+B/clk/CU, 16-byte writes 125), the clock under the fp32 GEMM
+(GRBM_GUI_ACTIVE), and the clock under sustained 16-bit MFMA work on random
+operands, which is power limited (a pure 32x32x16 MFMA loop sustains
+1.69-1.75 PFLOP/s, every instruction still 32 cycles: ~1.65 GHz).  16-bit
+and compensated launches use that clock for every term.  The model leaves
+out load latency and barrier waits, which it therefore underestimates for
+the 16-bit kernels (see the measured MFMA-busy fractions).
 """
 import math
 
 from . import _binding as B
 
 CUS = 256
-CLOCK_HZ = 2.38e9            # measured under load (GRBM_GUI_ACTIVE per XCD)
+CLOCK_HZ = 2.38e9            # measured under the fp32 GEMM (GRBM_GUI_ACTIVE per XCD)
+CLOCK_16BIT_HZ = 1.65e9      # power-limited clock under 16-bit MFMA work, random operands
 MFMA_FLOP_PER_CLK_CU = {"f32": 256.0, "16bit": 4096.0}
-LDS_B_PER_CLK_CU = 128.0
+LDS_WRITE_B_PER_CLK_CU = 128.0
+LDS_READ_B_PER_CLK_CU = 256.0
 VALU_OPS_PER_CLK_CU = 64.0   # 4 SIMDs x 16 lanes
 L2_B_PER_CLK_CU = 64.0
 HBM_B_PER_S = 8.0e12
@@ -53,7 +62,7 @@ TILES = {  # (MT, NT, KT, waves, workgroups per CU)
     ("f32", False): (128, 128, 32, 4, 2),
     ("f32", True): (256, 256, 32, 8, 1),   # KT 16 above four operand terms
     ("16bit", False): (128, 128, 32, 4, 2),
-    ("16bit", True): (256, 256, 32, 8, 1),
+    ("16bit", True): (256, 256, 64, 8, 1),  # KT 32 above four operand terms
     ("x3", False): (128, 128, 32, 4, 2),
     ("x3", True): (256, 256, 16, 8, 1),
 }
@@ -97,11 +106,14 @@ def predict(m, n, k, levels, kind="f32"):
         mt, nt, kt, waves, slots_per_cu = TILES[(kind, large)]
         if kind == "f32" and large and wa + wb > 4:
             kt = 16
+        if kind == "16bit" and large and wa + wb > 4:
+            kt = 32
         tiles = math.ceil(sm / mt) * math.ceil(sn / nt) * batch
         ktiles = math.ceil(sk / kt)
         wm, wn = (mt // 2, nt // (waves // 2))
         flops = 2.0 * mt * nt * kt * ktiles * tiles * mfma_mult
-        lds = ((mt + nt) * kt * b_lds * planes + waves * (wm + wn) * kt * b_lds * planes) * ktiles * tiles
+        lds_w = (mt + nt) * kt * b_lds * planes * ktiles * tiles
+        lds_r = waves * (wm + wn) * kt * b_lds * planes * ktiles * tiles
         l2 = (wa * mt + wb * nt) * kt * b_in * ktiles * tiles
 
         def staging(w):  # VALU lane-ops per element of one operand tile
@@ -112,11 +124,12 @@ def predict(m, n, k, levels, kind="f32"):
             return 0.125 if w == 1 else 2.0 * w + 0.5
         valu = (mt * staging(wa) + nt * staging(wb)) * kt * ktiles * tiles
         hbm = batch * (b_in * (wa * sm * sk + wb * sk * sn) + 8 * wc * sm * sn)
+        clock = CLOCK_HZ if kind == "f32" else CLOCK_16BIT_HZ
         t = {
-            "flop": flops / (CUS * MFMA_FLOP_PER_CLK_CU[rate_kind] * CLOCK_HZ),
-            "valu": valu / (CUS * VALU_OPS_PER_CLK_CU * CLOCK_HZ),
-            "lds": lds / (CUS * LDS_B_PER_CLK_CU * CLOCK_HZ),
-            "l2": l2 / (CUS * L2_B_PER_CLK_CU * CLOCK_HZ),
+            "flop": flops / (CUS * MFMA_FLOP_PER_CLK_CU[rate_kind] * clock),
+            "valu": valu / (CUS * VALU_OPS_PER_CLK_CU * clock),
+            "lds": (lds_w / LDS_WRITE_B_PER_CLK_CU + lds_r / LDS_READ_B_PER_CLK_CU) / (CUS * clock),
+            "l2": l2 / (CUS * L2_B_PER_CLK_CU * clock),
             "hbm": hbm / HBM_B_PER_S,
         }
         slots = CUS * slots_per_cu

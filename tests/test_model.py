@@ -76,7 +76,7 @@ def test_16bit_two_level_leaves_the_mfma_bound():
 def test_16bit_one_level_costs_more_than_it_saves():
     """16-bit MFMAs are so fast that forming two-term operand sums (a convert
     and an FMA per element) costs more than the eighth of the flops one level
-    saves: plain is predicted faster at 16384, as measured (8.9 ms plain, 12.7
+    saves: plain is predicted faster at 16384, as measured (8.4 ms plain, 12.2
     ms one level, bf16)."""
     n = 16384
     t0, _ = model.predict(n, n, n, 0, "16bit")
