@@ -11,7 +11,12 @@ effective rate of the headline level (--levels, default 1); all three levels
 are reported under "levels".  The roofline object describes the dominant
 kernel of the headline level, timed per launch with HIP events recorded by
 the library itself on the launch stream.  The CPU oracle is timed on a
-bounded sample of rows of the same product (cpu_baseline).
+bounded sample of rows of the same product (cpu_baseline); it is used
+nowhere else here: the sampled error checks compare against fp64 dot
+products computed in this script.  Secondary sections: the square and
+rank-k fp32 sweep, the awkward padded shapes, bf16 / fp16 / bf16x3 at
+4096-16384 (N(0,1) and rows/columns scaled over six decades),
+differentiation, and small sizes by schedule.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -46,6 +51,8 @@ def parse():
                    help="skip the bf16 / fp16 / bf16x3 section")
     p.add_argument("--no-autograd", action="store_true",
                    help="skip the forward + backward section")
+    p.add_argument("--no-sweep", action="store_true",
+                   help="skip the fp32 square / rank-k sweep and the awkward shapes")
     p.add_argument("--no-small", action="store_true",
                    help="skip the small-size schedule section")
     return p.parse_args()
@@ -139,53 +146,175 @@ def time_calls(fn, steps, warmup, stream):
     return e0.elapsed_time(e1) / steps
 
 
-def precision_section(N, steps, dev, stream, log):
-    """bf16 and fp16 operands and the compensated bf16x3 mode at m=n=k=N,
-    N(0,1) inputs, beta = 0: effective TFLOP/s per level and the sampled
-    error against the fp64 oracle on the stored operands."""
+def sampled_reference(A, B, C, rows, cols, alpha, beta):
+    """fp64 alpha * sum_l A[i,l] B[l,j] + beta * C[i,j] at the sampled (i, j),
+    one dot product per entry on the host, and the componentwise scale
+    |alpha| sum_l |A[i,l] B[l,j]| + |beta C[i,j]| of each entry.  A, B, C are
+    host or device tensors (only the sampled rows and columns are copied)."""
+    import torch
+    ri = torch.as_tensor(rows, device=A.device)
+    ci = torch.as_tensor(cols, device=B.device)
+    a = A[ri].double().cpu()
+    b = B[:, ci].double().cpu().t()
+    prod = a * b
+    val = alpha * prod.sum(dim=1)
+    mag = abs(alpha) * prod.abs().sum(dim=1)
+    if beta != 0.0:
+        c = C[torch.as_tensor(rows, device=C.device), torch.as_tensor(cols, device=C.device)]
+        c = c.double().cpu()
+        val = val + beta * c
+        mag = mag + abs(beta) * c.abs()
+    return val.numpy(), mag.numpy()
+
+
+def sampled_got(C, rows, cols):
+    import torch
+    return C[torch.as_tensor(rows, device=C.device),
+             torch.as_tensor(cols, device=C.device)].double().cpu().numpy()
+
+
+def precision_section(sizes, steps, dev, stream, log):
+    """bf16 and fp16 operands and the compensated bf16x3 mode at m=n=k in
+    `sizes`, beta = 0.  N(0,1) inputs: effective TFLOP/s per level and the
+    sampled errors.  Scaled inputs (rows of A and columns of B with 2-norms
+    spread over 1e-3..1e3): sampled errors only.  Errors against fp64 dot
+    products on the stored (rounded) operands, on 256 sampled entries:
+    e_norm (max |err| / (eps k max|A| max|B|)), relative Frobenius error of
+    the sample, and the componentwise maximum |err| / (eps sum_l |A_il B_lj|).
+    The inputs of the smaller sizes are the leading blocks of the largest."""
     import numpy as np
     import torch
-    import oracle
     import paper_1808_07984_amd as sg
     from paper_1808_07984_amd import inputs
 
-    A32 = inputs.normal(N, N, inputs.SEED_A)
-    B32 = inputs.normal(N, N, inputs.SEED_B)
-    rng = np.random.default_rng(1)
-    rows, cols = rng.integers(0, N, 256), rng.integers(0, N, 256)
-    ri, ci = torch.as_tensor(rows, device=dev), torch.as_tensor(cols, device=dev)
+    Nmax = max(sizes)
+    gens = {"normal": (inputs.normal(Nmax, Nmax, inputs.SEED_A), inputs.normal(Nmax, Nmax, inputs.SEED_B)),
+            "scaled": (inputs.scaled(Nmax, Nmax, inputs.SEED_A, axis=0),
+                       inputs.scaled(Nmax, Nmax, inputs.SEED_B, axis=1))}
     out = {}
     for name, tdt, mode, eps_gate in (("bf16", torch.bfloat16, "plain", 2.0 ** -7),
                                       ("f16", torch.float16, "plain", 2.0 ** -10),
                                       ("bf16x3", torch.float32, "bf16x3", 2.0 ** -16)):
-        Ah, Bh = A32.to(tdt), B32.to(tdt)
-        want = oracle.gemm_entries(Ah, Bh, None, rows, cols, 1.0, 0.0)
-        scale = N * float(Ah.float().abs().max()) * float(Bh.float().abs().max())
-        A, B = Ah.to(dev), Bh.to(dev)
-        C = torch.zeros(N, N, device=dev)
         res = {}
-        for L in (0, 1, 2):
-            def call():
-                sg.gemm(A, B, C, 1.0, 0.0, levels=L, mode=mode)
-            call()
-            torch.cuda.synchronize()
-            got = C[ri, ci].double().cpu().numpy()
-            err = float(np.abs(got - want).max())
-            ms = time_calls(call, steps, 1, stream)
-            info = sg.plan_info(N, N, N, L, tdt, mode)
-            mult = 3.0 if mode == "bf16x3" else 1.0
-            eff = 2.0 * N ** 3 / (ms * 1e-3) / 1e12
-            exe = mult * info.executed_flops / (ms * 1e-3) / 1e12
-            res["L%d" % L] = {"ms_per_step": round(ms, 4), "effective_tflops": round(eff, 2),
-                              "executed_mfma_tflops": round(exe, 2),
-                              "mfma_frac_executed": round(exe / BF16_MFMA_PEAK, 4),
-                              "e_norm_eps23": round(err / (2.0 ** -23 * scale), 3),
-                              "e_norm_gate": round(err / (eps_gate * scale), 4),
-                              "gate_eps": eps_gate, "tolerance": 2.0 ** (L + 1)}
-            log("%s L%d: %.3f ms  effective %.1f TFLOP/s  e_norm %.4f (gate eps %g)"
-                % (name, L, ms, eff, err / (eps_gate * scale), eps_gate))
+        for N in sizes:
+            rng = np.random.default_rng(N)
+            rows, cols = rng.integers(0, N, 256), rng.integers(0, N, 256)
+            for dist in ("normal", "scaled"):
+                Ah = gens[dist][0][:N, :N].contiguous().to(tdt)
+                Bh = gens[dist][1][:N, :N].contiguous().to(tdt)
+                want, mag = sampled_reference(Ah, Bh, None, rows, cols, 1.0, 0.0)
+                scale = N * float(Ah.float().abs().max()) * float(Bh.float().abs().max())
+                A, B = Ah.to(dev), Bh.to(dev)
+                C = torch.zeros(N, N, device=dev)
+                for L in (0, 1, 2):
+                    sg.gemm(A, B, C, 1.0, 0.0, levels=L, mode=mode)
+                    torch.cuda.synchronize()
+                    err = np.abs(sampled_got(C, rows, cols) - want)
+                    row = {"e_norm_gate": round(float(err.max()) / (eps_gate * scale), 5),
+                           "rel_frobenius": float(np.sqrt((err ** 2).sum() / (want ** 2).sum())),
+                           "componentwise_gate": round(float((err / (eps_gate * mag)).max()), 4),
+                           "gate_eps": eps_gate, "tolerance": 2.0 ** (L + 1)}
+                    if dist == "normal":
+                        ms = time_calls(lambda: sg.gemm(A, B, C, 1.0, 0.0, levels=L, mode=mode),
+                                        steps, 1, stream)
+                        info = sg.plan_info(N, N, N, L, tdt, mode)
+                        mult = 3.0 if mode == "bf16x3" else 1.0
+                        exe = mult * info.executed_flops / (ms * 1e-3) / 1e12
+                        row.update({"ms_per_step": round(ms, 4),
+                                    "effective_tflops": round(2.0 * N ** 3 / (ms * 1e-3) / 1e12, 2),
+                                    "executed_mfma_tflops": round(exe, 2),
+                                    "mfma_frac_executed": round(exe / BF16_MFMA_PEAK, 4)})
+                        log("%s N=%d L%d: %.3f ms  effective %.1f TFLOP/s  e_norm %.4f  rel_F %.2e"
+                            % (name, N, L, ms, row["effective_tflops"], row["e_norm_gate"],
+                               row["rel_frobenius"]))
+                    else:
+                        log("%s N=%d L%d scaled: e_norm %.4f  rel_F %.2e  componentwise %.3f"
+                            % (name, N, L, row["e_norm_gate"], row["rel_frobenius"],
+                               row["componentwise_gate"]))
+                    res.setdefault(str(N), {}).setdefault(dist, {})["L%d" % L] = row
+                del A, B, C
+                torch.cuda.empty_cache()
         out[name] = res
-        del A, B, C
+    return out
+
+
+def sweep_section(A, B, C0, steps, dev, stream, log):
+    """fp32 square sizes 2048-12288 and rank-k shapes m = n = 16384,
+    k = 512-4096, C := A*B + C at levels 0/1/2: effective TFLOP/s.  Operands
+    are copies (squares) or views (rank-k, leading dimension 16384) of the
+    seeded 16384 x 16384 benchmark inputs."""
+    import torch
+    import paper_1808_07984_amd as sg
+
+    out = {"square": {}, "rank_k": {}}
+    for N in (2048, 4096, 8192, 12288):
+        a, b = A[:N, :N].contiguous(), B[:N, :N].contiguous()
+        c0 = C0[:N, :N].contiguous()
+        c = c0.clone()
+        row = {}
+        for L in (0, 1, 2):
+            ms = time_calls(lambda: sg.gemm(a, b, c, 1.0, 1.0, levels=L), steps, 1, stream)
+            row["L%d" % L] = round(2.0 * N ** 3 / (ms * 1e-3) / 1e12, 2)
+        out["square"][str(N)] = row
+        log("sweep square %d: %s" % (N, row))
+        del a, b, c, c0
+    M = A.shape[0]
+    c = C0.clone()
+    for kk in (512, 1024, 2048, 4096):
+        a, b = A[:, :kk], B[:kk, :]
+        row = {}
+        for L in (0, 1, 2):
+            ms = time_calls(lambda: sg.gemm(a, b, c, 1.0, 1.0, levels=L), steps, 1, stream)
+            row["L%d" % L] = round(2.0 * M * M * kk / (ms * 1e-3) / 1e12, 2)
+        out["rank_k"][str(kk)] = row
+        log("sweep rank-k k=%d: %s" % (kk, row))
+    del c
+    torch.cuda.empty_cache()
+    return out
+
+
+def awkward_section(A, B, C0, steps, dev, stream, log):
+    """The padded awkward shapes (15001 x 17003 x 9007 with lda 9024,
+    ldb = ldc = 17024; 3000 x 20000 x 5000 with lda 5056, ldb = ldc = 20032;
+    padding holds NaN), alpha 1.5, beta 0.5, levels 0/1/2: effective TFLOP/s
+    and the sampled e_norm (fp32 eps, 256 entries).  Operands are the leading
+    blocks of the seeded benchmark inputs; B and C are continued along n past
+    their 16384 columns by repeating their leading columns."""
+    import numpy as np
+    import torch
+    import paper_1808_07984_amd as sg
+
+    out = {}
+    for (m, n, k, lda, ldb) in ((15001, 17003, 9007, 9024, 17024), (3000, 20000, 5000, 5056, 20032)):
+        Ap = torch.full((m, lda), float("nan"), device=dev)
+        Ap[:, :k] = A[:m, :k]
+        Bp = torch.full((k, ldb), float("nan"), device=dev)
+        w = min(n, B.shape[1])
+        Bp[:, :w] = B[:k, :w]
+        if n > w:
+            Bp[:, w:n] = B[:k, :n - w]
+        Cp = torch.full((m, ldb), float("nan"), device=dev)
+        Cp[:, :n] = C0[:m, :n] if n <= C0.shape[1] else torch.cat([C0[:m], C0[:m, :n - C0.shape[1]]], 1)
+        a, b, cin = Ap[:, :k], Bp[:, :n], Cp[:, :n].clone()
+        rng = np.random.default_rng(m)
+        rows, cols = rng.integers(0, m, 256), rng.integers(0, n, 256)
+        want, _ = sampled_reference(a, b, cin, rows, cols, 1.5, 0.5)
+        scale = 1.5 * k * float(a.abs().max()) * float(b.abs().max()) + 0.5 * float(cin.abs().max())
+        row = {}
+        for L in (0, 1, 2):
+            Cp[:, :n] = cin
+            sg.gemm(a, b, Cp[:, :n], 1.5, 0.5, levels=L)
+            torch.cuda.synchronize()
+            en = float(np.abs(sampled_got(Cp[:, :n], rows, cols) - want).max()) / (2.0 ** -23 * scale)
+            if not (en <= 2.0 ** (L + 1) and bool(torch.isfinite(Cp[:, :n]).all())):
+                raise SystemExit("parity failure: awkward %dx%dx%d levels=%d" % (m, n, k, L))
+            ms = time_calls(lambda: sg.gemm(a, b, Cp[:, :n], 1.5, 0.5, levels=L), steps, 1, stream)
+            row["L%d" % L] = {"effective_tflops": round(2.0 * m * n * k / (ms * 1e-3) / 1e12, 2),
+                              "ms_per_step": round(ms, 4), "sampled_e_norm": round(en, 4)}
+        key = "%dx%dx%d" % (m, n, k)
+        out[key] = row
+        log("awkward %s: %s" % (key, {L: v["effective_tflops"] for L, v in row.items()}))
+        del Ap, Bp, Cp, a, b, cin
         torch.cuda.empty_cache()
     return out
 
@@ -273,10 +402,9 @@ def main():
 
     # Sampled correctness check of each level on the benchmark inputs.
     import numpy as np
-    import oracle
     rng = np.random.default_rng(0)
     rows, cols = rng.integers(0, m, 256), rng.integers(0, n, 256)
-    want = oracle.gemm_entries(A_h, B_h, C_h, rows, cols, 1.0, 1.0)
+    want, _ = sampled_reference(A_h, B_h, C_h, rows, cols, 1.0, 1.0)
     scale = k * float(A_h.abs().max()) * float(B_h.abs().max()) + float(C_h.abs().max())
     parity = {}
     for L in (0, 1, 2):
@@ -364,12 +492,18 @@ def main():
                 "avg_launch_ms": round(dom_ms / dom_n, 4),
                 "flops_per_launch": dom_flops / dom_n}
 
+    sweep = awkward = None
+    if not args.no_sweep:
+        sweep = sweep_section(A, B, C0, max(1, min(args.steps, 3)), dev, stream, log)
+        awkward = awkward_section(A, B, C0, max(1, min(args.steps, 3)), dev, stream, log)
+
     precision = None
     if not args.no_precision:
-        log("precision section: bf16, fp16, bf16x3 at m=n=k=%d" % N)
+        sizes = tuple(s_ for s_ in (4096, 8192, N) if s_ <= N)
+        log("precision section: bf16, fp16, bf16x3 at m=n=k in %s" % (sizes,))
         del C0
         torch.cuda.empty_cache()
-        precision = precision_section(N, max(1, min(args.steps, 5)), dev, stream, log)
+        precision = precision_section(sizes, max(1, min(args.steps, 5)), dev, stream, log)
 
     small = None
     if not args.no_small:
@@ -407,9 +541,18 @@ def main():
         result["differentiation"] = {"workload": "StrassenMatmul forward + backward, fp32, "
                                                  "A,B ~ U[-1,1], dC ~ N(0,1); 6mnk flops per step",
                                      **autograd}
+    if sweep is not None:
+        result["sweep"] = {"workload": "fp32 C = A*B + C, A,B,C ~ U[-1,1] seeded; squares m=n=k=N "
+                                       "and rank-k m=n=16384; effective TFLOP/s per level", **sweep}
+    if awkward is not None:
+        result["awkward"] = {"workload": "fp32 C = 1.5*A*B + 0.5*C, NaN in the leading-dimension "
+                                         "padding, A,B,C ~ U[-1,1] seeded", **awkward}
     if precision is not None:
-        result["precision"] = {"workload": "A,B ~ N(0,1) seeded, C := A*B (beta 0), m=n=k=%d; "
-                                           "errors on 256 sampled entries vs the fp64 oracle" % N,
+        result["precision"] = {"workload": "C := A*B (beta 0), m=n=k in {4096, 8192, %d}; A,B ~ N(0,1) "
+                                           "seeded (timed) and rows of A / columns of B scaled to "
+                                           "2-norms over 1e-3..1e3 (errors only); errors on 256 "
+                                           "sampled entries vs fp64 dot products of the stored "
+                                           "operands" % N,
                                **precision}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
