@@ -149,16 +149,34 @@ std::atomic<int> g_tile{STRASSEN_TILE_AUTO};
 // Schedule of the products (strassen_set_schedule).
 std::atomic<int> g_schedule{STRASSEN_SCHEDULE_BATCHED};
 
-bool use_large(int64_t sm, int64_t sn, int batch) {
+bool use_large(int64_t sm, int64_t sn, int64_t sk, int batch, bool f32) {
     const int mode = g_tile.load(std::memory_order_relaxed);
     if (mode == STRASSEN_TILE_128) return false;
     if (mode == STRASSEN_TILE_256) return true;
-    // Measured on MI355X (fp32, levels 0-2, m = n = k = 8192 and 16384): the
-    // 256x256 tile is faster whenever each product still has >= 128 such
-    // tiles and the launch >= 256 (one per CU); below that the 128x128 tile's
-    // two workgroups per CU hide more latency.
     const int64_t per_product = ((sm + 255) / 256) * ((sn + 255) / 256);
-    return per_product >= 128 && per_product * batch >= 256;
+    if (!f32) {
+        // 16-bit operands: the 128x128 tile measured 25-40 % slower per flop,
+        // so the 256x256 tile is kept whenever it fills the CUs once.
+        return per_product >= 128 && per_product * batch >= 256;
+    }
+    // fp32: the launch runs in waves of workgroups (256 slots for the
+    // 256x256 tile, one per CU; 512 for the 128x128 tile, two per CU).  Cost
+    // of a wave in units of one k step of a 256x256 tile, fitted to MI355X
+    // measurements (squares 4096-16384, rank-k 16384^2 x 1024 and 2048,
+    // levels 0-2): sk + 62.5 for the 256x256 tile; 0.5 (1.045 sk + 16.5) for
+    // two 128x128 tiles sharing a CU (a quarter of the work each, 4.5 %
+    // slower per flop in the k loop, less fixed cost per tile), and 0.65 of
+    // that for a last wave with at most one of them per CU.  The cheaper
+    // shape is taken.
+    const int64_t tiles256 = per_product * batch;
+    const int64_t tiles128 = ((sm + 127) / 128) * ((sn + 127) / 128) * batch;
+    const double k = (double)sk;
+    const double cost256 = (double)((tiles256 + 255) / 256) * (k + 62.5);
+    const double pair = 0.5 * (1.045 * k + 16.5);
+    const int64_t full128 = tiles128 / 512, rest128 = tiles128 % 512;
+    const double cost128 = (double)full128 * pair +
+                           (rest128 == 0 ? 0.0 : rest128 <= 256 ? 0.65 * pair : pair);
+    return cost256 <= cost128;
 }
 
 // Kernel family of a call: fp32 MFMA, or the 16-bit MFMA path.
@@ -210,7 +228,7 @@ int run_concurrent(const Call &c, const Plan &plan, bool vec) {
     Recorder &rec = recorder();
     for (int first = 0, launch = 0; first < total; first += strassen::kMaxBatchArgs, ++launch) {
         const int batch = std::min(strassen::kMaxBatchArgs, total - first);
-        const bool large = use_large(plan.sm, plan.sn, batch);
+        const bool large = use_large(plan.sm, plan.sn, plan.sk, batch, true);
         const strassen::KernelShape ks = strassen::f32_tile_shape(large);
         a.tiles_m = (int32_t)((plan.sm + ks.mt - 1) / ks.mt);
         a.tiles_n = (int32_t)((plan.sn + ks.nt - 1) / ks.nt);
@@ -313,7 +331,7 @@ int run(const Call &c) {
     for (size_t bi = 0; bi < plan.batches.size(); ++bi) {
         const strassen::Batch &bt = plan.batches[bi];
         const int batch = (int)bt.products.size();
-        const bool large = use_large(plan.sm, plan.sn, batch);
+        const bool large = use_large(plan.sm, plan.sn, plan.sk, batch, !fam.m16);
         const strassen::KernelShape ks = shape_of(fam, large);
         a.tiles_m = (int32_t)((plan.sm + ks.mt - 1) / ks.mt);
         a.tiles_n = (int32_t)((plan.sn + ks.nt - 1) / ks.nt);
@@ -475,7 +493,7 @@ int run_hybrid(const Call &c, float *ws) {
             const strassen::Batch &bt = in.batches[bi];
             const int batch = (int)bt.products.size();
             const int wc = bt.wc * tp.nc;
-            const bool large = use_large(sm, sn, batch);
+            const bool large = use_large(sm, sn, sk, batch, true);
             const strassen::KernelShape ks = strassen::f32_tile_shape(large);
             a.tiles_m = (int32_t)((sm + ks.mt - 1) / ks.mt);
             a.tiles_n = (int32_t)((sn + ks.nt - 1) / ks.nt);
@@ -674,7 +692,7 @@ int strassen_plan_info(int64_t m, int64_t n, int64_t k, int levels, strassen_dty
         const strassen::Batch *wide = &p.batches[0];
         for (const strassen::Batch &b : p.batches)
             if (b.wa + b.wb > wide->wa + wide->wb) wide = &b;
-        const bool large = use_large(p.sm, p.sn, (int)wide->products.size());
+        const bool large = use_large(p.sm, p.sn, p.sk, (int)wide->products.size(), !fam.m16);
         const strassen::KernelShape ks = shape_of(fam, large);
         std::memset(out, 0, sizeof(*out));
         out->levels = levels;

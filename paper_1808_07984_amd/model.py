@@ -80,9 +80,17 @@ def _batches(levels):
     return [tuple(out[i]) for i in sorted(out)]
 
 
-def _use_large(sm, sn, batch):
+def _use_large(sm, sn, sk, batch, f32):
+    """The library's automatic tile choice (wave-cost comparison for fp32)."""
     per = math.ceil(sm / 256) * math.ceil(sn / 256)
-    return per >= 128 and per * batch >= 256
+    if not f32:
+        return per >= 128 and per * batch >= 256
+    t128 = math.ceil(sm / 128) * math.ceil(sn / 128) * batch
+    cost256 = math.ceil(per * batch / 256) * (sk + 62.5)
+    pair = 0.5 * (1.045 * sk + 16.5)
+    full, rest = divmod(t128, 512)
+    cost128 = full * pair + (0.0 if rest == 0 else 0.65 * pair if rest <= 256 else pair)
+    return cost256 <= cost128
 
 
 def predict(m, n, k, levels, kind="f32"):
@@ -102,7 +110,7 @@ def predict(m, n, k, levels, kind="f32"):
     launches = []
     total = 0.0
     for wa, wb, wc, batch in _batches(levels):
-        large = _use_large(sm, sn, batch)
+        large = _use_large(sm, sn, sk, batch, kind == "f32")
         mt, nt, kt, waves, slots_per_cu = TILES[(kind, large)]
         if kind == "f32" and large and wa + wb > 4:
             kt = 16
