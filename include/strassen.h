@@ -133,10 +133,14 @@ int64_t strassen_hybrid_workspace_size(int64_t m, int64_t n, int64_t k);
  * NULL = the null stream).  Always returns 0. */
 int strassen_set_stream(void *hip_stream);
 
-/* Workgroup tile of the product kernels.  AUTO (the default) picks 256x256
- * when every product of a launch has at least 128 such tiles and the launch at
- * least 256, else 128x128; the others force one shape for every launch
- * (tuning, tests).  Process-wide; returns 0 or -1 (bad value). */
+/* Workgroup tile of the product kernels.  AUTO (the default) picks per
+ * launch: for fp32, 256x256 or 128x128 by the lower cost of the launch's waves
+ * of workgroups (256 slots of 256x256, one per CU, against 512 of 128x128,
+ * two per CU; per-wave costs fitted to MI355X measurements); for 16-bit
+ * operands, 256x256 when every product of the launch has at least 128 such
+ * tiles and the launch at least 256, else 128x128.  The others force one
+ * shape for every launch (tuning, tests).  Process-wide; returns 0 or -1
+ * (bad value). */
 #define STRASSEN_TILE_AUTO 0
 #define STRASSEN_TILE_128 1
 #define STRASSEN_TILE_256 2
@@ -166,10 +170,12 @@ typedef struct {
                                   * vector width for levels >= 1) */
     int32_t n_instances;       /* 7^levels products */
     int32_t n_launches;        /* race-free batches = kernel launches */
-    int32_t tile_m, tile_n, tile_k; /* workgroup tile of the product kernel (tile_k:
-                                     * variants with at most four operand terms;
-                                     * above that the 256x256 fp32 kernels use 16,
-                                     * the 16-bit ones 32) */
+    int32_t tile_m, tile_n, tile_k; /* workgroup tile of the launch with the most
+                                     * operand terms (the tile is chosen per
+                                     * launch; tile_k: variants with at most
+                                     * four operand terms; above that the
+                                     * 256x256 fp32 kernels use 16, the 16-bit
+                                     * ones 32) */
     int32_t workgroups_per_instance;
     double executed_flops;     /* 7^L * 2 * sub_m * sub_n * sub_k */
     double classical_flops;    /* 2 * m * n * k */

@@ -93,3 +93,34 @@ def test_compensated_mode_triples_the_flop_term():
     _, f = model.predict(n, n, n, 0, "16bit")
     _, x = model.predict(n, n, n, 0, "x3")
     assert math.isclose(x[0]["t_flop"], 3 * f[0]["t_flop"], rel_tol=1e-12)
+
+
+# Automatic tile choice: the library picks, per launch, the tile whose waves
+# of workgroups cost less; the model mirrors that rule.  plan_info reports the
+# tile of the launch with the most operand terms.
+@pytest.mark.parametrize("m,n,k", [(16384, 16384, 16384), (12288, 12288, 12288), (10240, 10240, 10240),
+                                   (8192, 8192, 8192), (6144, 6144, 6144), (4096, 4096, 4096),
+                                   (16384, 16384, 1024), (15001, 17003, 9007), (3000, 20000, 5000),
+                                   (1024, 1024, 1024)])
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_tile_choice_matches_model(m, n, k, levels):
+    info = sg.plan_info(m, n, k, levels)
+    rc, ins = sg.strassen_plan_instances(levels)
+    assert rc >= 0
+    launches = {}
+    for p in ins:
+        w = launches.setdefault(p.launch, [p.n_a + p.n_b, 0])
+        w[1] += 1
+    terms, batch = max(launches.values(), key=lambda v: v[0])
+    widest = [b for t, b in launches.values() if t == terms][0]
+    large = model._use_large(info.sub_m, info.sub_n, info.sub_k, widest, True)
+    assert info.tile_m == (256 if large else 128)
+
+
+@pytest.mark.parametrize("m,levels,tile", [(16384, 0, 256), (16384, 1, 256), (12288, 0, 256),
+                                           (10240, 0, 128), (6144, 0, 128), (6144, 2, 128),
+                                           (4096, 0, 256), (1024, 0, 128)])
+def test_tile_choice_measured_cases(m, levels, tile):
+    """Shapes where the faster tile was measured on MI355X (fp32): full 256x256
+    waves keep 256x256; 4.5-wave or 2.25-wave launches take 128x128."""
+    assert sg.plan_info(m, m, m, levels).tile_m == tile
