@@ -281,15 +281,19 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
     };
 
     // Form the signed operand sums and store them into LDS buffer `buf`.
+    // The sign of each operand's first term is factored out of its sum and
+    // applied in the epilogue (signs are +-1, so the staged values change by
+    // that exact negation only): the stored sum is x_0 + sum_t (s_t s_0) x_t,
+    // and a single-term operand is stored as loaded.
     auto store_operand = [&](auto stage, auto xt, float *tile, f32x4 (*raw)[decltype(stage)::VECS],
                              auto nterms, int n_use, const TermArg *terms) __attribute__((always_inline)) {
         using S = decltype(stage);
         constexpr int NT_ = decltype(nterms)::value;
         auto sum = [&](int p) __attribute__((always_inline)) {
-            f32x4 v = raw[0][p] * terms[0].sign;
+            f32x4 v = raw[0][p];
 #pragma unroll
             for (int t = 1; t < NT_; ++t)
-                if (t < n_use) v += raw[t][p] * terms[t].sign;
+                if (t < n_use) v += raw[t][p] * (terms[t].sign * terms[0].sign);
             return v;
         };
         if constexpr (decltype(xt)::value) {
@@ -455,7 +459,8 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
         __syncthreads();
     }
 
-    // Epilogue: C_o += sign_o * alpha * M for every output block; the first
+    // Epilogue: C_o += sign_o * s_a0 * s_b0 * alpha * M' for every output
+    // block (M' the product of the sign-folded operand sums); the first
     // update of a block in launch order applies beta instead of reading C
     // twice.  32x32 accumulator layout: lane l, register r holds row
     // 8*(r/4) + 4*(l/32) + r%4, column l%32.  Each accumulator element is
@@ -469,7 +474,7 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
     int crows[WC], ccols[WC], cfirst[WC];
 #pragma unroll
     for (int o = 0; o < WC; ++o) {
-        g[o] = P.c[o].sign * alpha;
+        g[o] = P.c[o].sign * (P.a[0].sign * P.b[0].sign) * alpha;
         coff[o] = P.c[o].off;
         crows[o] = P.c[o].rows;
         ccols[o] = P.c[o].cols;
