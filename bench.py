@@ -13,10 +13,10 @@ kernel of the headline level, timed per launch with HIP events recorded by
 the library itself on the launch stream.  The CPU oracle is timed on a
 bounded sample of rows of the same product (cpu_baseline); it is used
 nowhere else here: the sampled error checks compare against fp64 dot
-products computed in this script.  Secondary sections: the square and
-rank-k fp32 sweep, the awkward padded shapes, bf16 / fp16 / bf16x3 at
-4096-16384 (N(0,1) and rows/columns scaled over six decades),
-differentiation, and small sizes by schedule.
+products computed in this script.  Secondary sections: bf16 / fp16 /
+bf16x3 at 4096-16384 (N(0,1) and rows/columns scaled over six decades),
+differentiation, small sizes by schedule, and with --sweep the square and
+rank-k fp32 sweep and the awkward padded shapes.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -51,8 +51,10 @@ def parse():
                    help="skip the bf16 / fp16 / bf16x3 section")
     p.add_argument("--no-autograd", action="store_true",
                    help="skip the forward + backward section")
-    p.add_argument("--no-sweep", action="store_true",
-                   help="skip the fp32 square / rank-k sweep and the awkward shapes")
+    p.add_argument("--sweep", action="store_true",
+                   help="also time the fp32 square / rank-k sweep and the awkward shapes (off by "
+                        "default: the rank-k launches share kernel and grid with the headline's, "
+                        "which would mix them in per-kernel profiles of the default run)")
     p.add_argument("--no-small", action="store_true",
                    help="skip the small-size schedule section")
     return p.parse_args()
@@ -493,7 +495,7 @@ def main():
                 "flops_per_launch": dom_flops / dom_n}
 
     sweep = awkward = None
-    if not args.no_sweep:
+    if args.sweep:
         sweep = sweep_section(A, B, C0, max(1, min(args.steps, 3)), dev, stream, log)
         awkward = awkward_section(A, B, C0, max(1, min(args.steps, 3)), dev, stream, log)
 
