@@ -310,8 +310,12 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
     const int64_t a_step = (int64_t)sizeof(In) * (A_KC ? (int64_t)C::KT : (int64_t)C::KT * lda);
     const int64_t b_step = (int64_t)sizeof(In) * (B_KC ? (int64_t)C::KT : (int64_t)C::KT * ldb);
 
+    // Loads number (t * VECS + p) * LOADS + l of one operand, those in
+    // [lo, hi) only (the steady loop spreads one k-tile's loads over the
+    // MFMA steps of the previous one).
     auto load_fast = [&](auto &raw, const In *base, const TermArg *terms, auto stage, auto nterms,
-                         const auto &off, int64_t org, int64_t step, int kt) __attribute__((always_inline)) {
+                         const auto &off, int64_t org, int64_t step, int kt, int lo = 0,
+                         int hi = 1 << 20) __attribute__((always_inline)) {
         using S = decltype(stage);
         constexpr int NT_ = decltype(nterms)::value;
 #pragma unroll
@@ -322,14 +326,31 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
 #pragma unroll
                 for (int p = 0; p < S::VECS; ++p)
 #pragma unroll
-                    for (int l = 0; l < S::LOADS; ++l) raw[t][p][l] = buffer_load16<V>(r, off[p][l]);
+                    for (int l = 0; l < S::LOADS; ++l) {
+                        const int idx = (t * S::VECS + p) * S::LOADS + l;
+                        if (idx >= lo && idx < hi) raw[t][p][l] = buffer_load16<V>(r, off[p][l]);
+                    }
             } else {
 #pragma unroll
                 for (int p = 0; p < S::VECS; ++p)
 #pragma unroll
-                    for (int l = 0; l < S::LOADS; ++l)
-                        raw[t][p][l] = *reinterpret_cast<const V *>(tb + off[p][l]);
+                    for (int l = 0; l < S::LOADS; ++l) {
+                        const int idx = (t * S::VECS + p) * S::LOADS + l;
+                        if (idx >= lo && idx < hi) raw[t][p][l] = *reinterpret_cast<const V *>(tb + off[p][l]);
+                    }
             }
+        }
+    };
+    constexpr int NLA = WA * SA::VECS * SA::LOADS, NLB = WB * SB::VECS * SB::LOADS;
+    // Loads [lo, hi) of the k-tile's flat list (A's, then B's).
+    auto load_fast_range = [&](int kt, int lo, int hi) __attribute__((always_inline)) {
+        if constexpr (kFastLoop) {
+            if (lo < NLA)
+                load_fast(raw_a, A, P.a, SA{}, std::integral_constant<int, WA>{}, a_off, a_org, a_step, kt,
+                          lo, hi);
+            if (hi > NLA)
+                load_fast(raw_b, B, P.b, SB{}, std::integral_constant<int, WB>{}, b_off, b_org, b_step, kt,
+                          lo - NLA, hi - NLA);
         }
     };
     auto stage_load_fast_into = [&](int kt, auto &ra, auto &rb) __attribute__((always_inline)) {
@@ -512,9 +533,9 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
         const u32x2 hi2 = *reinterpret_cast<const u32x2 *>(tile + S::at(x, k + 4));
         return u32x4{lo2.x, lo2.y, hi2.x, hi2.y};
     };
-    auto compute = [&](int buf) __attribute__((always_inline)) {
-#pragma unroll
-        for (int s = 0; s < C::KT / 16; ++s) {
+    // MFMA step s (16 consecutive k) of the k-tile in LDS buffer `buf`.
+    auto compute_step = [&](int buf, int s) __attribute__((always_inline)) {
+        {
             u32x4 af[NPLANES][C::BM], bf[NPLANES][C::BN];
 #pragma unroll
             for (int q = 0; q < NPLANES; ++q) {
@@ -536,6 +557,10 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
                     }
                 }
         }
+    };
+    auto compute = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+        for (int s = 0; s < C::KT / 16; ++s) compute_step(buf, s);
     };
 
     const int nk = (args.sk + C::KT - 1) / C::KT;
@@ -576,16 +601,22 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
         stage_store(0);
         __syncthreads();
     }
-    // Steady state: the next k-tile is in bounds.  The scheduling barriers
-    // keep its loads ahead of the MFMA block and the sums behind it, so the
-    // load latency is covered by a whole k-tile of MFMAs.
+    // Steady state: the next k-tile is in bounds.  Its loads are spread
+    // evenly over the MFMA steps of the current one (issued all at once,
+    // they filled the texture-address queue and stalled the waves' MFMA
+    // issue: +4-11 % measured), and its sums follow the whole MFMA block;
+    // the scheduling barriers hold that order.
     if constexpr (kFastLoop)
     for (; kt + 1 < nfast; ++kt) {
         const int cur = kt & 1;
-        stage_load_fast(kt + 1);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(cur);
-        __builtin_amdgcn_sched_barrier(0);
+        constexpr int NS = C::KT / 16, NL = NLA + NLB;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            load_fast_range(kt + 1, s * NL / NS, (s + 1) * NL / NS);
+            __builtin_amdgcn_sched_barrier(0);
+            compute_step(cur, s);
+            __builtin_amdgcn_sched_barrier(0);
+        }
         stage_store(cur ^ 1);
         __syncthreads();
     }
