@@ -342,16 +342,19 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
         }
     };
     constexpr int NLA = WA * SA::VECS * SA::LOADS, NLB = WB * SB::VECS * SB::LOADS;
-    // Loads [lo, hi) of the k-tile's flat list (A's, then B's).
-    auto load_fast_range = [&](int kt, int lo, int hi) __attribute__((always_inline)) {
+    // Loads [lo, hi) of the k-tile's flat list (A's, then B's) into ra / rb.
+    auto load_fast_range_into = [&](int kt, auto &ra, auto &rb, int lo, int hi) __attribute__((always_inline)) {
         if constexpr (kFastLoop) {
             if (lo < NLA)
-                load_fast(raw_a, A, P.a, SA{}, std::integral_constant<int, WA>{}, a_off, a_org, a_step, kt,
+                load_fast(ra, A, P.a, SA{}, std::integral_constant<int, WA>{}, a_off, a_org, a_step, kt,
                           lo, hi);
             if (hi > NLA)
-                load_fast(raw_b, B, P.b, SB{}, std::integral_constant<int, WB>{}, b_off, b_org, b_step, kt,
+                load_fast(rb, B, P.b, SB{}, std::integral_constant<int, WB>{}, b_off, b_org, b_step, kt,
                           lo - NLA, hi - NLA);
         }
+    };
+    auto load_fast_range = [&](int kt, int lo, int hi) __attribute__((always_inline)) {
+        load_fast_range_into(kt, raw_a, raw_b, lo, hi);
     };
     auto stage_load_fast_into = [&](int kt, auto &ra, auto &rb) __attribute__((always_inline)) {
         if constexpr (kFastLoop) {
@@ -562,6 +565,39 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
 #pragma unroll
         for (int s = 0; s < C::KT / 16; ++s) compute_step(buf, s);
     };
+    // The same MFMA block with the loads of k-tile `lkt` into ra / rb issued
+    // in groups between its rows of MFMAs (fragments are read first).
+    auto compute_loading = [&](int buf, int lkt, auto &ra, auto &rb) __attribute__((always_inline)) {
+        constexpr int NG = (C::KT / 16) * C::BM, NL = NLA + NLB;
+#pragma unroll
+        for (int s = 0; s < C::KT / 16; ++s) {
+            u32x4 af[NPLANES][C::BM], bf[NPLANES][C::BN];
+#pragma unroll
+            for (int q = 0; q < NPLANES; ++q) {
+#pragma unroll
+                for (int i = 0; i < C::BM; ++i)
+                    af[q][i] = frag(&As[buf][q][0], SA{}, wm * C::WM + i * 32 + l32, 16 * s + 8 * h);
+#pragma unroll
+                for (int j = 0; j < C::BN; ++j)
+                    bf[q][j] = frag(&Bs[buf][q][0], SB{}, wn * C::WN + j * 32 + l32, 16 * s + 8 * h);
+            }
+#pragma unroll
+            for (int i = 0; i < C::BM; ++i) {
+                const int g = s * C::BM + i;
+                load_fast_range_into(lkt, ra, rb, g * NL / NG, (g + 1) * NL / NG);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int j = 0; j < C::BN; ++j) {
+                    acc[i][j] = mfma(af[0][i], bf[0][j], acc[i][j]);
+                    if constexpr (Ops::kX3) {
+                        acc[i][j] = mfma(af[0][i], bf[NPLANES - 1][j], acc[i][j]);
+                        acc[i][j] = mfma(af[NPLANES - 1][i], bf[0][j], acc[i][j]);
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    };
 
     const int nk = (args.sk + C::KT - 1) / C::KT;
     int kt = 0;
@@ -576,16 +612,10 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
         stage_load_fast(1);
         __syncthreads();
         for (; kt + 3 < nfast; kt += 2) {
-            stage_load_fast_into(kt + 2, q_a, q_b);
-            __builtin_amdgcn_sched_barrier(0);
-            compute(0);
-            __builtin_amdgcn_sched_barrier(0);
+            compute_loading(0, kt + 2, q_a, q_b);
             stage_store_from(1, raw_a, raw_b);
             __syncthreads();
-            stage_load_fast_into(kt + 3, raw_a, raw_b);
-            __builtin_amdgcn_sched_barrier(0);
-            compute(1);
-            __builtin_amdgcn_sched_barrier(0);
+            compute_loading(1, kt + 3, raw_a, raw_b);
             stage_store_from(0, q_a, q_b);
             __syncthreads();
         }
