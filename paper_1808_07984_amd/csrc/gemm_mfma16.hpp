@@ -46,7 +46,10 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 // KT + 8 (the eight rows of one 16-byte read cycle land in distinct bank
 // groups), paired tiles KT + 4 (32 consecutive columns fall on 32 distinct
 // even banks for the 8-byte reads, and the 4-byte staging stores of one wave
-// on 64 distinct banks); SQ_LDS_BANK_CONFLICT measures 0 for these kernels.
+// on 64 distinct banks).  SQ_LDS_BANK_CONFLICT measures 0 for the 64-deep
+// multi-term kernels, and 0.7-0.9 conflict cycles per LDS instruction for
+// the 32-deep, compensated and swizzled single-term ones (LDS bandwidth is
+// not what limits them).
 template <int MT_, int NT_, int KT_, int WAVES_M_, int WAVES_N_, int GROUP_>
 struct Cfg {
     static constexpr int MT = MT_, NT = NT_, KT = KT_;
@@ -127,8 +130,10 @@ struct Stage {
     // texture-address queue of these buffer-load kernels for 13 % of their
     // cycles).  The staging stores of one wave then hit rows 8 apart; the
     // 4-element groups of each LDS row are XOR-swizzled with (x / 32) mod 8,
-    // which keeps both those stores and the fragment reads free of bank
-    // conflicts (64 banks of 4 bytes, checked for KT = 32 and 64).  Summed
+    // which spreads those stores and the fragment reads over all 64 banks of
+    // a 64-bank, 4-byte model (checked for KT = 32 and 64; the hardware
+    // counts 0.7 conflict cycles per LDS instruction, the change measured
+    // +4 % for bf16 W = 1).  Summed
     // operands keep the k-major unit order: there the swizzled fragment
     // addresses cost registers the staging needs.
     static constexpr bool SWZ = !DIRECT && NV == 8 && X >= 256 && ONE_TERM;
