@@ -170,12 +170,10 @@ typedef struct {
                                   * vector width for levels >= 1) */
     int32_t n_instances;       /* 7^levels products */
     int32_t n_launches;        /* race-free batches = kernel launches */
-    int32_t tile_m, tile_n, tile_k; /* workgroup tile of the launch with the most
-                                     * operand terms (the tile is chosen per
-                                     * launch; tile_k: variants with at most
-                                     * four operand terms; above that the
-                                     * 256x256 fp32 kernels use 16, the 16-bit
-                                     * ones 32) */
+    int32_t tile_m, tile_n, tile_k; /* workgroup tile and k-tile depth of the
+                                     * launch with the most operand terms,
+                                     * for untransposed operands (both are
+                                     * chosen per launch) */
     int32_t workgroups_per_instance;
     double executed_flops;     /* 7^L * 2 * sub_m * sub_n * sub_k */
     double classical_flops;    /* 2 * m * n * k */

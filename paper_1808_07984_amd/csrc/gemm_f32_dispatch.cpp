@@ -3,9 +3,10 @@
 
 namespace strassen {
 
-KernelShape f32_tile_shape(bool large) {
-    // k-tile of the variants with at most four operand terms (more: 16)
-    return large ? KernelShape{256, 256, 32, 4} : KernelShape{128, 128, 32, 4};
+KernelShape f32_tile_shape(bool large, int terms) {
+    // k-tile by operand terms (W_A + W_B): the large tile stages 16 deep above
+    // four terms, 32 otherwise
+    return large ? KernelShape{256, 256, terms > 4 ? 16 : 32, 4} : KernelShape{128, 128, 32, 4};
 }
 
 hipError_t launch_f32(bool trans_a, bool trans_b, bool large, int wa, int wb, int wc,

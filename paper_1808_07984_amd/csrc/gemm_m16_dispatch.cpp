@@ -3,10 +3,15 @@
 
 namespace strassen {
 
-KernelShape m16_tile_shape(bool x3, bool large) {
-    // 16-byte loads cover 8 elements of a 16-bit type or 4 fp32.
-    // k-tile of the variants with at most four operand terms (more: 32)
-    if (large) return KernelShape{256, 256, x3 ? 16 : 64, x3 ? 4 : 8};
+KernelShape m16_tile_shape(bool x3, bool large, int terms, bool untransposed) {
+    // 16-byte loads cover 8 elements of a 16-bit type or 4 fp32.  k-tile of
+    // the large tiles by operand terms (W_A + W_B): 16-bit 64 up to four,
+    // 32 above; compensated 32 for the untransposed single-term product, 16
+    // otherwise.
+    if (large) {
+        const int kt = x3 ? (terms == 2 && untransposed ? 32 : 16) : (terms <= 4 ? 64 : 32);
+        return KernelShape{256, 256, kt, x3 ? 4 : 8};
+    }
     return KernelShape{128, 128, 32, x3 ? 4 : 8};
 }
 

@@ -283,7 +283,7 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
     // next tile's loads.  Measured +4-6 % for (1,1,1), (2,1,2), (2,2,1) and
     // (2,2,2); for bf16/fp16 operands (64-deep k-tiles) it measured 1-3 %
     // slower and is not used.
-    constexpr bool kDeep = kFastLoop && Ops::kX3 && WA + WB <= 4 && C::MT == 256;
+    constexpr bool kDeep = kFastLoop && Ops::kX3 && WA + WB <= 4 && C::MT == 256 && C::KT == 16;
     // Buffer loads for single-term operands and the two-ahead loop (measured
     // faster there); otherwise plain global loads measured faster.
     constexpr bool kBufferLoads = WA + WB <= 2 || kDeep;
@@ -755,17 +755,24 @@ hipError_t launch_variant(const LaunchArgs &a, int batch, bool vec, hipStream_t 
 // 16-bit large tiles stage 64-deep k-tiles when the variant has at most four
 // operand terms: one k-tile is then about 2000 MFMA cycles per SIMD, which
 // amortises the barrier and the first LDS reads of each k-tile; with more
-// terms the staging registers allow 32.
-template <class C, class Ops, int WA, int WB>
-using TileFor = typename std::conditional<std::is_same<C, Large>::value && !Ops::kX3 && WA + WB <= 4,
-                                          LargeK64, C>::type;
+// terms the staging registers allow 32.  The compensated mode's single-term
+// product with A and B as stored takes a 32-deep k-tile with the loads
+// spread over its two MFMA steps (A, k-contiguous, then loads whole 128-byte
+// rows: +3 % against the 16-deep two-ahead loop, which stays faster, by
+// 6-8 %, for the multi-term products; the transposed layouts were not
+// measured and keep 16).
+template <class C, class Ops, int WA, int WB, bool A_KC = false, bool B_KC = true>
+using TileFor = typename std::conditional<
+    std::is_same<C, Large>::value && !Ops::kX3 && WA + WB <= 4, LargeK64,
+    typename std::conditional<std::is_same<C, LargeX3>::value && WA + WB == 2 && A_KC && !B_KC, Large,
+                              C>::type>::type;
 
 template <class C, class Ops, bool A_KC, bool B_KC>
 hipError_t dispatch(int wa, int wb, int wc, const LaunchArgs &a, int batch, bool vec,
                     hipStream_t s) {
 #define STRASSEN_CASE(X, Y, Z)        \
     if (wa == X && wb == Y && wc == Z) \
-        return launch_variant<TileFor<C, Ops, X, Y>, Ops, A_KC, B_KC, X, Y, Z>(a, batch, vec, s);
+        return launch_variant<TileFor<C, Ops, X, Y, A_KC, B_KC>, Ops, A_KC, B_KC, X, Y, Z>(a, batch, vec, s);
     STRASSEN_CASE(1, 1, 1)
     STRASSEN_CASE(2, 2, 2)
     STRASSEN_CASE(2, 2, 1)

@@ -15,7 +15,7 @@ struct KernelShape {
 // fp32 operands, fp32 MFMA.  Launches one batch of `batch` products of
 // variant (wa, wb, wc); vec = 16-byte loads are aligned (see api.cpp);
 // trans_x = operand stored transposed; large = 256x256 tile (else 128x128).
-KernelShape f32_tile_shape(bool large);
+KernelShape f32_tile_shape(bool large, int terms = 2);
 hipError_t launch_f32(bool trans_a, bool trans_b, bool large, int wa, int wb, int wc,
                       const LaunchArgs &a, int batch, bool vec, hipStream_t s);
 const char *f32_kernel_name(bool large);
@@ -41,7 +41,7 @@ hipError_t launch_f32_conc_l(int wmax, const LaunchArgs &a, int batch, bool vec,
 // bf16 hi/lo pairs (compensated product hi*hi + hi*lo + lo*hi).  Transposed
 // operands exist for the compensated mode only.  large = 256x256 tile.
 enum class Operand16 { kBf16, kF16, kBf16x3 };
-KernelShape m16_tile_shape(bool x3, bool large);
+KernelShape m16_tile_shape(bool x3, bool large, int terms = 2, bool untransposed = true);
 hipError_t launch_m16(Operand16 op, bool trans_a, bool trans_b, bool large, int wa, int wb, int wc,
                       const LaunchArgs &a, int batch, bool vec, hipStream_t s);
 const char *m16_kernel_name(Operand16 op, bool large);

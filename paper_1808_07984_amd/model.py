@@ -116,6 +116,8 @@ def predict(m, n, k, levels, kind="f32"):
             kt = 16
         if kind == "16bit" and large and wa + wb > 4:
             kt = 32
+        if kind == "x3" and large and wa + wb == 2:
+            kt = 32
         tiles = math.ceil(sm / mt) * math.ceil(sn / nt) * batch
         ktiles = math.ceil(sk / kt)
         wm, wn = (mt // 2, nt // (waves // 2))
