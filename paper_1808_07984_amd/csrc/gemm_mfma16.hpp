@@ -46,10 +46,9 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 // KT + 8 (the eight rows of one 16-byte read cycle land in distinct bank
 // groups), paired tiles KT + 4 (32 consecutive columns fall on 32 distinct
 // even banks for the 8-byte reads, and the 4-byte staging stores of one wave
-// on 64 distinct banks).  SQ_LDS_BANK_CONFLICT measures 0 for the 64-deep
-// multi-term kernels, and 0.7-0.9 conflict cycles per LDS instruction for
-// the 32-deep, compensated and swizzled single-term ones (LDS bandwidth is
-// not what limits them).
+// on 64 distinct banks).  SQ_LDS_BANK_CONFLICT measures 0.7-0.9 conflict
+// cycles per LDS instruction for these kernels (1.8 for the 32-deep
+// compensated single-term one); LDS bandwidth is not what limits them.
 template <int MT_, int NT_, int KT_, int WAVES_M_, int WAVES_N_, int GROUP_>
 struct Cfg {
     static constexpr int MT = MT_, NT = NT_, KT = KT_;
@@ -114,7 +113,8 @@ struct X3Ops {
 
 // Staging geometry of one operand (X = MT or NT rows of the [x][k] tile).
 // direct: units of one x row and NV consecutive k; paired: units of two
-// consecutive k rows and NV consecutive x.
+// consecutive k rows and NV consecutive x (X / NV / 8 and KT / 16 whole
+// blocks of 8 x 8 units).
 template <class C, class Ops, int X, bool DIRECT, bool ONE_TERM>
 struct Stage {
     static constexpr int NV = Ops::NV;
@@ -124,6 +124,7 @@ struct Stage {
     static constexpr int VECS = UNITS / C::THREADS;  // units per thread per term
     static constexpr int LOADS = DIRECT ? 1 : 2;     // global vectors per unit
     static_assert(VECS * C::THREADS == UNITS, "tile split");
+    static_assert(DIRECT || ((X / NV) % 8 == 0 && (C::KT / 2) % 8 == 0), "8 x 8 unit blocks");
     // Single-term paired 16-bit tiles 256 wide: consecutive lanes take
     // consecutive x units of one k row pair, so one load instruction covers
     // two rows (8 cache lines instead of 32; the 32-row spread filled the
@@ -133,9 +134,18 @@ struct Stage {
     // which spreads those stores and the fragment reads over all 64 banks of
     // a 64-bank, 4-byte model (checked for KT = 32 and 64; the hardware
     // counts 0.7 conflict cycles per LDS instruction, the change measured
-    // +4 % for bf16 W = 1).  Summed
-    // operands keep the k-major unit order: there the swizzled fragment
-    // addresses cost registers the staging needs.
+    // +4 % for bf16 W = 1).  Other paired tiles (summed operands, whose
+    // staging needs the registers that swizzled fragment addresses would
+    // take, and narrower or compensated ones) give each wave an 8 x 8 block
+    // of (k row pair, x unit): lanes 0-7 step through the row pairs, so one
+    // load instruction covers 8 rows of 128 contiguous bytes (8 cache
+    // lines; the earlier k-major order spread it over 16-32 rows).
+    // Measured +4 % (2,2,1), +6 % (2,2,2), +2 % (1,2,2), +2-3 % for the
+    // four-term operands, results bit-identical.  The hardware counts 0.9
+    // bank-conflict cycles per LDS instruction for these kernels (0 for the
+    // k-major order): lanes x units 4 apart share banks, and the store of
+    // lanes 0-15 appears to be served together with lanes 32-47.  Reordering
+    // the x units across lanes to separate them measured no faster.
     static constexpr bool SWZ = !DIRECT && NV == 8 && X >= 256 && ONE_TERM;
 
     // Unit p of thread tid: first (x, k) it covers.
@@ -150,9 +160,11 @@ struct Stage {
             x = (u % PER_ROW) * NV;
             k = 2 * (u / PER_ROW);
         } else {
-            constexpr int PAIRS = C::KT / 2;
-            k = 2 * (u % PAIRS);
-            x = (u / PAIRS) * NV;
+            // each wave: 8 row pairs x 8 consecutive 16-byte x units
+            constexpr int XB = X / NV / 8;
+            const int b = u / 64, lane = u % 64;
+            x = NV * (8 * (b % XB) + lane / 8);
+            k = 2 * (8 * (b / XB) + lane % 8);
         }
     }
     // Offset of element (x, k) in the tile (paired layouts: k even or a
