@@ -377,6 +377,12 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
     };
 
     const int nk = (args.sk + KT - 1) / KT;
+    // Scheduling-group sizes of the steady loop below: LDS fragment reads
+    // per 8-deep chunk, 16-byte LDS stores per k-tile, MFMAs per store.
+    constexpr int kFragReads = BM * ((A_KC || A_XT) ? 1 : 4) + BN * ((B_KC || B_XT) ? 1 : 4);
+    constexpr int kStores = SA::VECS + SB::VECS;
+    constexpr int kMfmaPerStore = (4 * BM * BN) / kStores > 0 ? (4 * BM * BN) / kStores : 1;
+    static_assert(KT / 8 >= 2, "two chunks per k-tile");
     // Staggered staging (16-deep large tiles, i.e. variants with more than
     // four operand terms): A's terms are loaded and summed first, then B's,
     // so only one operand's raw terms occupy registers at a time (+3-6 %
@@ -421,19 +427,34 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
         store_b(cur ^ 1);
         __syncthreads();
     }
+    if constexpr (!kStagger)
     for (; kt + 1 < nfast; ++kt) {
         const int cur = kt & 1;
         issue_fast(kt + 1);
-        // Loads first, then all but the last chunk of MFMAs, then the sums
-        // and LDS stores of the next k-tile (its buffer is idle), then the
-        // last chunk: the loads have most of a k-tile to land, and the MFMA
-        // pipe still has work while the sums are formed.  The scheduling
+        // Loads first, then the MFMAs of all but the last two chunks, then
+        // the next-to-last chunk with the sums and LDS stores of the next
+        // k-tile (its buffer is idle) woven between its MFMAs, then the last
+        // chunk: the loads have half a k-tile or more to land, and the
+        // stores, a burst of ~64 KB per CU when every wave issued them at
+        // once, now trickle out between MFMAs (+1.4 % W = 1, +1.3-3.2 % for
+        // the one-level variants, results bit-identical).  The scheduling
         // barriers keep that order (left to itself the scheduler moves the
         // sums next to the loads and exposes their latency).
         __builtin_amdgcn_sched_barrier(0);
-        compute(cur, 0, KT / 8 - 1);
+        compute(cur, 0, KT / 8 - 2);
         __builtin_amdgcn_sched_barrier(0);
+        compute(cur, KT / 8 - 2, KT / 8 - 1);
         sum_store(cur ^ 1);
+        // that chunk's fragment reads, then per 16-byte store: a share of
+        // the chunk's MFMAs, up to four sums, the store
+        __builtin_amdgcn_sched_group_barrier(0x100, kFragReads, 0);
+#pragma unroll
+        for (int i = 0; i < kStores; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, kMfmaPerStore, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, 4 * BM * BN, 0);
         __builtin_amdgcn_sched_barrier(0);
         compute(cur, KT / 8 - 1, KT / 8);
         __syncthreads();
