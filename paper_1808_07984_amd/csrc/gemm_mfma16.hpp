@@ -411,8 +411,10 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
 
     // Signed sums of the raw terms ra / rb rounded to the MFMA type (split
     // into hi/lo for the compensated mode), stored into LDS buffer `buf`.
-    auto stage_store_from = [&](int buf, auto &ra, auto &rb) __attribute__((always_inline)) {
+    // part: 0 both operands, 1 A only, 2 B only.
+    auto stage_store_from = [&](int buf, auto &ra, auto &rb, int part = 0) __attribute__((always_inline)) {
         // ---- A ----
+        if (part != 2)
 #pragma unroll
         for (int p = 0; p < SA::VECS; ++p) {
             int x, k;
@@ -469,6 +471,7 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
             }
         }
         // ---- B ----
+        if (part != 1)
 #pragma unroll
         for (int p = 0; p < SB::VECS; ++p) {
             int x, k;
@@ -653,18 +656,50 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
     // they filled the texture-address queue and stalled the waves' MFMA
     // issue: +4-11 % measured), and its sums follow the whole MFMA block;
     // the scheduling barriers hold that order.
+    // Single-term 16-bit products on 64-deep k-tiles: A's loads are issued
+    // in the first steps, so its LDS stores are woven between the MFMAs of
+    // the last step (per 16-byte store: a share of the step's MFMAs, up to
+    // 8 VALU instructions, the store) and only B's follow the MFMA block:
+    // +4-5 % bf16 and fp16 in short runs, about +1 % in long ones, where the
+    // power limit takes part of it back through the clock; results
+    // bit-identical.  Elsewhere it measured 10-17 %
+    // slower ((2,2,x), (4,4,2)), -1 % (128x128 tiles) or within the noise
+    // (other summed operands, the compensated mode), so those keep the
+    // stores after the block.
+    constexpr bool kWeaveA = WA + WB == 2 && !Ops::kX3 && C::KT == 64;
     if constexpr (kFastLoop)
     for (; kt + 1 < nfast; ++kt) {
         const int cur = kt & 1;
         constexpr int NS = C::KT / 16, NL = NLA + NLB;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
+        for (int s = 0; s < (kWeaveA ? NS - 1 : NS); ++s) {
             load_fast_range(kt + 1, s * NL / NS, (s + 1) * NL / NS);
             __builtin_amdgcn_sched_barrier(0);
             compute_step(cur, s);
             __builtin_amdgcn_sched_barrier(0);
         }
-        stage_store(cur ^ 1);
+        if constexpr (kWeaveA) {
+            load_fast_range(kt + 1, (NS - 1) * NL / NS, NL);
+            __builtin_amdgcn_sched_barrier(0);
+            compute_step(cur, NS - 1);
+            stage_store_from(cur ^ 1, raw_a, raw_b, 1);
+            constexpr int kFrags = NPLANES * (C::BM * SA::LOADS + C::BN * SB::LOADS);
+            constexpr int kStoresA = SA::VECS * NPLANES * (SA::LOADS == 1 ? 1 : NV);
+            constexpr int kMfmas = C::BM * C::BN * (Ops::kX3 ? 3 : 1);
+            constexpr int kMfmaPerStore = kMfmas / kStoresA > 0 ? kMfmas / kStoresA : 1;
+            __builtin_amdgcn_sched_group_barrier(0x100, kFrags, 0);
+#pragma unroll
+            for (int i = 0; i < kStoresA; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, kMfmaPerStore, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);
+                __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, kMfmas, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            stage_store_from(cur ^ 1, raw_a, raw_b, 2);
+        } else {
+            stage_store(cur ^ 1);
+        }
         __syncthreads();
     }
     // Remaining k-tiles (fringe workgroups, a ragged last k-tile).
