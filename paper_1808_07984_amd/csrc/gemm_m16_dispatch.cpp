@@ -3,13 +3,15 @@
 
 namespace strassen {
 
-KernelShape m16_tile_shape(bool x3, bool large, int terms, bool untransposed) {
+KernelShape m16_tile_shape(bool x3, bool large, int wa, int wb, bool untransposed) {
     // 16-byte loads cover 8 elements of a 16-bit type or 4 fp32.  k-tile of
-    // the large tiles by operand terms (W_A + W_B): 16-bit 64 up to four,
-    // 32 above; compensated 32 for the untransposed single-term product, 16
-    // otherwise.
+    // the large tiles by operand terms: 16-bit 64 up to four in all, 32
+    // above and for (1,2,2); compensated 32 for the untransposed
+    // single-term product, 16 otherwise.
     if (large) {
-        const int kt = x3 ? (terms == 2 && untransposed ? 32 : 16) : (terms <= 4 ? 64 : 32);
+        const int terms = wa + wb;
+        const int kt = x3 ? (terms == 2 && untransposed ? 32 : 16)
+                          : (terms <= 4 && !(wa == 1 && wb == 2) ? 64 : 32);
         return KernelShape{256, 256, kt, x3 ? 4 : 8};
     }
     return KernelShape{128, 128, 32, x3 ? 4 : 8};

@@ -293,9 +293,22 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
     // two k-tiles ahead (a second set of staging registers): its 16-deep
     // k-tile is ~1500 MFMA cycles per SIMD, shorter than the latency of the
     // next tile's loads.  Measured +4-6 % for (1,1,1), (2,1,2), (2,2,1) and
-    // (2,2,2); for bf16/fp16 operands (64-deep k-tiles) it measured 1-3 %
-    // slower and is not used.
-    constexpr bool kDeep = kFastLoop && Ops::kX3 && WA + WB <= 4 && C::MT == 256 && C::KT == 16;
+    // (2,2,2).  For bf16/fp16 operands it is used for (1,2,2) only, on
+    // 32-deep k-tiles (the same registers as one 64-deep set): +8.5 %
+    // against the 64-deep one-ahead loop; (2,1,2) and (2,2,2) measured 3-5 %
+    // slower, (2,2,1) and W = 1 within 1 %.
+    constexpr bool kDeep = kFastLoop && C::MT == 256 &&
+                           (Ops::kX3 ? (WA + WB <= 4 && C::KT == 16) : (WA == 1 && WB == 2 && C::KT == 32));
+    // In the two-ahead loop the stores of the tile loaded one trip earlier
+    // go to the buffer whose last reads ended at the previous barrier, so
+    // they are woven between the MFMA rows (A's after the second row, B's
+    // after the row past the middle) instead of following them: for the
+    // compensated mode +2.6-3.0 % (2,1,2), +0.7-0.8 % (2,2,x) with A and B
+    // as stored, +0.7 % / +5.6 % with both transposed, -1 % (1,2,2) and
+    // -0.1 to -1.1 % with exactly one operand transposed; bit-identical.
+    // Used where W_A >= W_B and either both or neither operand is
+    // transposed.
+    constexpr bool kWeaveDeep = kDeep && Ops::kX3 && WA >= WB && A_KC != B_KC;
     // Buffer loads for single-term operands and the two-ahead loop (measured
     // faster there); otherwise plain global loads measured faster.
     constexpr bool kBufferLoads = WA + WB <= 2 || kDeep;
@@ -586,8 +599,13 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
         for (int s = 0; s < C::KT / 16; ++s) compute_step(buf, s);
     };
     // The same MFMA block with the loads of k-tile `lkt` into ra / rb issued
-    // in groups between its rows of MFMAs (fragments are read first).
-    auto compute_loading = [&](int buf, int lkt, auto &ra, auto &rb) __attribute__((always_inline)) {
+    // in groups between its rows of MFMAs (fragments are read first); with
+    // sa / sb given, the staged sums of sa / sb are stored into LDS buffer
+    // `sbuf` between the rows too (A's after the second row, B's after the
+    // row past the middle).
+    auto compute_loading = [&](int buf, int lkt, auto &ra, auto &rb, int sbuf = -1,
+                               V (*sa)[SA::VECS][SA::LOADS] = nullptr,
+                               V (*sb)[SB::VECS][SB::LOADS] = nullptr) __attribute__((always_inline)) {
         constexpr int NG = (C::KT / 16) * C::BM, NL = NLA + NLB;
 #pragma unroll
         for (int s = 0; s < C::KT / 16; ++s) {
@@ -605,6 +623,8 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
             for (int i = 0; i < C::BM; ++i) {
                 const int g = s * C::BM + i;
                 load_fast_range_into(lkt, ra, rb, g * NL / NG, (g + 1) * NL / NG);
+                if (sa != nullptr && g == 1) stage_store_from(sbuf, sa, sb, 1);
+                if (sa != nullptr && g == NG / 2 + 1) stage_store_from(sbuf, sa, sb, 2);
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int j = 0; j < C::BN; ++j) {
@@ -632,12 +652,19 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
         stage_load_fast(1);
         __syncthreads();
         for (; kt + 3 < nfast; kt += 2) {
-            compute_loading(0, kt + 2, q_a, q_b);
-            stage_store_from(1, raw_a, raw_b);
-            __syncthreads();
-            compute_loading(1, kt + 3, raw_a, raw_b);
-            stage_store_from(0, q_a, q_b);
-            __syncthreads();
+            if constexpr (kWeaveDeep) {
+                compute_loading(0, kt + 2, q_a, q_b, 1, raw_a, raw_b);
+                __syncthreads();
+                compute_loading(1, kt + 3, raw_a, raw_b, 0, q_a, q_b);
+                __syncthreads();
+            } else {
+                compute_loading(0, kt + 2, q_a, q_b);
+                stage_store_from(1, raw_a, raw_b);
+                __syncthreads();
+                compute_loading(1, kt + 3, raw_a, raw_b);
+                stage_store_from(0, q_a, q_b);
+                __syncthreads();
+            }
         }
         compute(0);
         stage_store_from(1, raw_a, raw_b);
@@ -802,7 +829,8 @@ hipError_t launch_variant(const LaunchArgs &a, int batch, bool vec, hipStream_t 
 // 16-bit large tiles stage 64-deep k-tiles when the variant has at most four
 // operand terms: one k-tile is then about 2000 MFMA cycles per SIMD, which
 // amortises the barrier and the first LDS reads of each k-tile; with more
-// terms the staging registers allow 32.  The compensated mode's single-term
+// terms the staging registers allow 32, and (1,2,2) takes 32 for its
+// two-ahead loop.  The compensated mode's single-term
 // product with A and B as stored takes a 32-deep k-tile with the loads
 // spread over its two MFMA steps (A, k-contiguous, then loads whole 128-byte
 // rows: +3 % against the 16-deep two-ahead loop, which stays faster, by
@@ -810,7 +838,7 @@ hipError_t launch_variant(const LaunchArgs &a, int batch, bool vec, hipStream_t 
 // measured and keep 16).
 template <class C, class Ops, int WA, int WB, bool A_KC = false, bool B_KC = true>
 using TileFor = typename std::conditional<
-    std::is_same<C, Large>::value && !Ops::kX3 && WA + WB <= 4, LargeK64,
+    std::is_same<C, Large>::value && !Ops::kX3 && WA + WB <= 4 && !(WA == 1 && WB == 2), LargeK64,
     typename std::conditional<std::is_same<C, LargeX3>::value && WA + WB == 2 && A_KC && !B_KC, Large,
                               C>::type>::type;
 

@@ -41,7 +41,7 @@ hipError_t launch_f32_conc_l(int wmax, const LaunchArgs &a, int batch, bool vec,
 // bf16 hi/lo pairs (compensated product hi*hi + hi*lo + lo*hi).  Transposed
 // operands exist for the compensated mode only.  large = 256x256 tile.
 enum class Operand16 { kBf16, kF16, kBf16x3 };
-KernelShape m16_tile_shape(bool x3, bool large, int terms = 2, bool untransposed = true);
+KernelShape m16_tile_shape(bool x3, bool large, int wa = 1, int wb = 1, bool untransposed = true);
 hipError_t launch_m16(Operand16 op, bool trans_a, bool trans_b, bool large, int wa, int wb, int wc,
                       const LaunchArgs &a, int batch, bool vec, hipStream_t s);
 const char *m16_kernel_name(Operand16 op, bool large);

@@ -62,7 +62,7 @@ TILES = {  # (MT, NT, KT, waves, workgroups per CU)
     ("f32", False): (128, 128, 32, 4, 2),
     ("f32", True): (256, 256, 32, 8, 1),   # KT 16 above four operand terms
     ("16bit", False): (128, 128, 32, 4, 2),
-    ("16bit", True): (256, 256, 64, 8, 1),  # KT 32 above four operand terms
+    ("16bit", True): (256, 256, 64, 8, 1),  # KT 32 above four operand terms and for (1,2,2)
     ("x3", False): (128, 128, 32, 4, 2),
     ("x3", True): (256, 256, 16, 8, 1),
 }
@@ -114,7 +114,7 @@ def predict(m, n, k, levels, kind="f32"):
         mt, nt, kt, waves, slots_per_cu = TILES[(kind, large)]
         if kind == "f32" and large and wa + wb > 4:
             kt = 16
-        if kind == "16bit" and large and wa + wb > 4:
+        if kind == "16bit" and large and (wa + wb > 4 or (wa, wb) == (1, 2)):
             kt = 32
         if kind == "x3" and large and wa + wb == 2:
             kt = 32
