@@ -294,9 +294,10 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
     // k-tile is ~1500 MFMA cycles per SIMD, shorter than the latency of the
     // next tile's loads.  Measured +4-6 % for (1,1,1), (2,1,2), (2,2,1) and
     // (2,2,2).  For bf16/fp16 operands it is used for (1,2,2) only, on
-    // 32-deep k-tiles (the same registers as one 64-deep set): +8.5 %
-    // against the 64-deep one-ahead loop; (2,1,2) and (2,2,2) measured 3-5 %
-    // slower, (2,2,1) and W = 1 within 1 %.
+    // 32-deep k-tiles (the same registers as one 64-deep set): +6-9 %
+    // against the 64-deep one-ahead loop in three A/B runs; (2,1,2) and
+    // (2,2,2) measured 3-5 % slower with it, (2,2,1) within 1 %, W = 1 1-3 %
+    // slower.
     constexpr bool kDeep = kFastLoop && C::MT == 256 &&
                            (Ops::kX3 ? (WA + WB <= 4 && C::KT == 16) : (WA == 1 && WB == 2 && C::KT == 32));
     // In the two-ahead loop the stores of the tile loaded one trip earlier
