@@ -45,7 +45,7 @@ def _load():
     if _lib is not None:
         return _lib
     if not os.path.exists(_LIB_PATH):
-        from . import build as _build  # building the checker is not using it
+        from . import build as _build  # compiles oracle.c with gcc on first use
         _build.build()
     lib = ctypes.CDLL(_LIB_PATH)
     lib.oracle_gemm_f64.argtypes = [_i64, _i64, _i64, _dp, _i64, _dp, _i64,
