@@ -195,9 +195,9 @@ Family family(strassen_dtype_t t, strassen_mode_t mode) {
     return Family{true, op, strassen::m16_tile_shape(op == Operand16::kBf16x3, false).vec};
 }
 
-strassen::KernelShape shape_of(const Family &f, bool large, int wa, int wb, bool untransposed) {
+strassen::KernelShape shape_of(const Family &f, bool large, int wa, int wb, int wc, bool untransposed) {
     return f.m16 ? strassen::m16_tile_shape(f.op == strassen::Operand16::kBf16x3, large, wa, wb, untransposed)
-                 : strassen::f32_tile_shape(large, wa + wb);
+                 : strassen::f32_tile_shape(large, wa, wb, wc, untransposed);
 }
 
 // Task-parallel schedule for small problems (Task Parallelism section,
@@ -332,7 +332,7 @@ int run(const Call &c) {
         const strassen::Batch &bt = plan.batches[bi];
         const int batch = (int)bt.products.size();
         const bool large = use_large(plan.sm, plan.sn, plan.sk, batch, !fam.m16);
-        const strassen::KernelShape ks = shape_of(fam, large, bt.wa, bt.wb, !c.trans_a && !c.trans_b);
+        const strassen::KernelShape ks = shape_of(fam, large, bt.wa, bt.wb, bt.wc, !c.trans_a && !c.trans_b);
         a.tiles_m = (int32_t)((plan.sm + ks.mt - 1) / ks.mt);
         a.tiles_n = (int32_t)((plan.sn + ks.nt - 1) / ks.nt);
         for (int z = 0; z < batch; ++z) {
@@ -693,7 +693,7 @@ int strassen_plan_info(int64_t m, int64_t n, int64_t k, int levels, strassen_dty
         for (const strassen::Batch &b : p.batches)
             if (b.wa + b.wb > wide->wa + wide->wb) wide = &b;
         const bool large = use_large(p.sm, p.sn, p.sk, (int)wide->products.size(), !fam.m16);
-        const strassen::KernelShape ks = shape_of(fam, large, wide->wa, wide->wb, true);
+        const strassen::KernelShape ks = shape_of(fam, large, wide->wa, wide->wb, wide->wc, true);
         std::memset(out, 0, sizeof(*out));
         out->levels = levels;
         out->blocks_per_dim = p.d;

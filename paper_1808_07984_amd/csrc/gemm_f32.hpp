@@ -247,6 +247,29 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
             }
         }
     };
+    // Loads of terms [t0, t1) only (the split staging below).
+    auto issue_fast_a_terms = [&](int kt, int t0, int t1) __attribute__((always_inline)) {
+#pragma unroll
+        for (int t = 0; t < WA; ++t) {
+            if (t >= t0 && t < t1) {
+                const auto r = raw_rsrc(reinterpret_cast<const char *>(A + P.a[t].off + a_org) +
+                                        a_step * kt);
+#pragma unroll
+                for (int p = 0; p < SA::VECS; ++p) raw_a[t][p] = buffer_load16<f32x4>(r, a_off[p]);
+            }
+        }
+    };
+    auto issue_fast_b_terms = [&](int kt, int t0, int t1) __attribute__((always_inline)) {
+#pragma unroll
+        for (int t = 0; t < WB; ++t) {
+            if (t >= t0 && t < t1) {
+                const auto r = raw_rsrc(reinterpret_cast<const char *>(B + P.b[t].off + b_org) +
+                                        b_step * kt);
+#pragma unroll
+                for (int p = 0; p < SB::VECS; ++p) raw_b[t][p] = buffer_load16<f32x4>(r, b_off[p]);
+            }
+        }
+    };
     auto issue_fast = [&](int kt) __attribute__((always_inline)) {
         issue_fast_a(kt);
         issue_fast_b(kt);
@@ -444,7 +467,52 @@ void strassen_f32_kernel(const LaunchArgs args, const int vec_flag) {
         store_b(cur ^ 1);
         __syncthreads();
     }
-    if constexpr (!kStagger)
+    // Split staging (32-deep large tiles with more than four operand terms,
+    // the (4,1,4) and (4,2,2) variants): each operand's terms are loaded two
+    // at a time and the second folded into the first term's registers
+    // before the next two are loaded, so at most the partial sum and two raw
+    // terms are live; the additions keep the order of the plain sum (results
+    // bit-identical to the 16-deep kernels).  +4.3 % (4,1,4), +5.6 % (4,2,2)
+    // against the 16-deep staggered loop; the other four-term variants
+    // spill 130-660 more bytes this way and measured up to 21 % slower.
+    constexpr bool kSplit = std::is_same<Cfg, Large>::value && WA + WB > 4 && !CONC;
+    if constexpr (kSplit)
+    for (; kt + 1 < nfast; ++kt) {
+        const int cur = kt & 1;
+        constexpr int HA = WA > 2 ? 2 : WA, HB = WB > 2 ? 2 : WB;
+        issue_fast_a_terms(kt + 1, 0, HA);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(cur, 0, 1);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (WA > 2) {
+#pragma unroll
+            for (int p = 0; p < SA::VECS; ++p) raw_a[0][p] += raw_a[1][p] * (P.a[1].sign * P.a[0].sign);
+#pragma unroll
+            for (int p = 0; p < SA::VECS; ++p) raw_a[1][p] = f32x4{0.f, 0.f, 0.f, 0.f};
+            issue_fast_a_terms(kt + 1, 2, WA);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        compute(cur, 1, 2);
+        __builtin_amdgcn_sched_barrier(0);
+        store_a(cur ^ 1);
+        issue_fast_b_terms(kt + 1, 0, HB);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(cur, 2, 3);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (WB > 2) {
+#pragma unroll
+            for (int p = 0; p < SB::VECS; ++p) raw_b[0][p] += raw_b[1][p] * (P.b[1].sign * P.b[0].sign);
+#pragma unroll
+            for (int p = 0; p < SB::VECS; ++p) raw_b[1][p] = f32x4{0.f, 0.f, 0.f, 0.f};
+            issue_fast_b_terms(kt + 1, 2, WB);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        compute(cur, 3, 4);
+        __builtin_amdgcn_sched_barrier(0);
+        store_b(cur ^ 1);
+        __syncthreads();
+    }
+    if constexpr (!kStagger && !kSplit)
     for (; kt + 1 < nfast; ++kt) {
         const int cur = kt & 1;
         issue_fast(kt + 1);
@@ -597,10 +665,14 @@ hipError_t launch_variant(const LaunchArgs &a, int batch, bool vec, hipStream_t 
 // Concurrent schedule: up to two (one level) or four (two levels) terms per
 // operand and output, counts read per product.
 // Large tiles take the 16-deep k-tile when the variant has more than four
-// operand terms.
-template <class Cfg, int WA, int WB>
-using TileFor = typename std::conditional<std::is_same<Cfg, Large>::value && (WA + WB > 4),
-                                          LargeK16, Cfg>::type;
+// operand terms, except (4,1,4) and (4,2,2) with A and B as stored, which
+// take the 32-deep k-tile with split staging.
+template <int WA, int WB, int WC, bool A_KC, bool B_KC>
+constexpr bool kSplitVariant = A_KC && !B_KC && WA == 4 && ((WB == 1 && WC == 4) || (WB == 2 && WC == 2));
+template <class Cfg, int WA, int WB, int WC = 1, bool A_KC = true, bool B_KC = false>
+using TileFor = typename std::conditional<
+    std::is_same<Cfg, Large>::value && (WA + WB > 4) && !kSplitVariant<WA, WB, WC, A_KC, B_KC>, LargeK16,
+    Cfg>::type;
 
 template <class Cfg>
 hipError_t dispatch_concurrent(int wmax, const LaunchArgs &a, int batch, bool vec, hipStream_t s) {
@@ -613,7 +685,7 @@ hipError_t dispatch(int wa, int wb, int wc, const LaunchArgs &a, int batch, bool
                     hipStream_t s) {
 #define STRASSEN_CASE(X, Y, Z)        \
     if (wa == X && wb == Y && wc == Z) \
-        return launch_variant<TileFor<Cfg, X, Y>, A_KC, B_KC, X, Y, Z>(a, batch, vec, s);
+        return launch_variant<TileFor<Cfg, X, Y, Z, A_KC, B_KC>, A_KC, B_KC, X, Y, Z>(a, batch, vec, s);
     // plain GEMM and the one-level variants
     STRASSEN_CASE(1, 1, 1)
     STRASSEN_CASE(2, 2, 2)

@@ -3,10 +3,12 @@
 
 namespace strassen {
 
-KernelShape f32_tile_shape(bool large, int terms) {
-    // k-tile by operand terms (W_A + W_B): the large tile stages 16 deep above
-    // four terms, 32 otherwise
-    return large ? KernelShape{256, 256, terms > 4 ? 16 : 32, 4} : KernelShape{128, 128, 32, 4};
+KernelShape f32_tile_shape(bool large, int wa, int wb, int wc, bool untransposed) {
+    // k-tile by operand terms: the large tile stages 16 deep above four terms
+    // in all, except (4,1,4) and (4,2,2) with untransposed operands (32 deep,
+    // split staging), and 32 deep otherwise
+    const bool split = untransposed && wa == 4 && ((wb == 1 && wc == 4) || (wb == 2 && wc == 2));
+    return large ? KernelShape{256, 256, wa + wb > 4 && !split ? 16 : 32, 4} : KernelShape{128, 128, 32, 4};
 }
 
 hipError_t launch_f32(bool trans_a, bool trans_b, bool large, int wa, int wb, int wc,

@@ -15,7 +15,7 @@ struct KernelShape {
 // fp32 operands, fp32 MFMA.  Launches one batch of `batch` products of
 // variant (wa, wb, wc); vec = 16-byte loads are aligned (see api.cpp);
 // trans_x = operand stored transposed; large = 256x256 tile (else 128x128).
-KernelShape f32_tile_shape(bool large, int terms = 2);
+KernelShape f32_tile_shape(bool large, int wa = 1, int wb = 1, int wc = 1, bool untransposed = true);
 hipError_t launch_f32(bool trans_a, bool trans_b, bool large, int wa, int wb, int wc,
                       const LaunchArgs &a, int batch, bool vec, hipStream_t s);
 const char *f32_kernel_name(bool large);

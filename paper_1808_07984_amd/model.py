@@ -60,7 +60,7 @@ LAUNCH_S = 6e-6
 
 TILES = {  # (MT, NT, KT, waves, workgroups per CU)
     ("f32", False): (128, 128, 32, 4, 2),
-    ("f32", True): (256, 256, 32, 8, 1),   # KT 16 above four operand terms
+    ("f32", True): (256, 256, 32, 8, 1),   # KT 16 above four operand terms but (4,1,4), (4,2,2)
     ("16bit", False): (128, 128, 32, 4, 2),
     ("16bit", True): (256, 256, 64, 8, 1),  # KT 32 above four operand terms and for (1,2,2)
     ("x3", False): (128, 128, 32, 4, 2),
@@ -112,7 +112,7 @@ def predict(m, n, k, levels, kind="f32"):
     for wa, wb, wc, batch in _batches(levels):
         large = _use_large(sm, sn, sk, batch, kind == "f32")
         mt, nt, kt, waves, slots_per_cu = TILES[(kind, large)]
-        if kind == "f32" and large and wa + wb > 4:
+        if kind == "f32" and large and wa + wb > 4 and (wa, wb, wc) not in ((4, 1, 4), (4, 2, 2)):
             kt = 16
         if kind == "16bit" and large and (wa + wb > 4 or (wa, wb) == (1, 2)):
             kt = 32
