@@ -160,7 +160,8 @@ def tile_mode(request):
 @pytest.mark.parametrize("tile_mode", [sg.STRASSEN_TILE_128, sg.STRASSEN_TILE_256], indirect=True)
 @pytest.mark.parametrize("kind", sorted(MODES))
 @pytest.mark.parametrize("levels", [0, 1, 2])
-@pytest.mark.parametrize("m,n,k", [(3, 5, 7), (65, 67, 63), (301, 257, 190), (520, 700, 333)])
+@pytest.mark.parametrize("m,n,k", [(3, 5, 7), (65, 67, 63), (301, 257, 190), (520, 700, 333),
+                                   (1100, 1060, 600)])
 def test_lowp_integer_exact_each_tile(tile_mode, kind, levels, m, n, k):
     dtype, mode = MODES[kind]
     prob = make_problem(m, n, k, kind="integers", dtype=dtype, c_kind="integers")

@@ -294,8 +294,11 @@ TILES = [sg.STRASSEN_TILE_128, sg.STRASSEN_TILE_256]
 @pytest.mark.parametrize("tile_mode", TILES, indirect=True)
 @pytest.mark.parametrize("levels", [0, 1, 2])
 @pytest.mark.parametrize("m,n,k", [(1, 1, 1), (3, 5, 7), (65, 67, 63), (301, 257, 190),
-                                   (520, 700, 333)])
+                                   (520, 700, 333), (1100, 1060, 600)])
 def test_integer_exact_each_tile(tile_mode, m, n, k, levels):
+    # 1100 x 1060 x 600: at two levels the 275 x 265 x 150 blocks still have
+    # interior 256 x 256 tiles with several in-bounds k-tiles, so the
+    # steady-state loops of every two-level variant run and are checked exactly
     prob = make_problem(m, n, k, kind="integers", c_kind="integers")
     dev = _run(prob, levels, 1.0, 1.0)
     want = oracle.gemm_f64(prob["A"], prob["B"], prob["C"], 1.0, 1.0)
