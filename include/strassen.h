@@ -129,6 +129,45 @@ int strassen_gemm_hybrid(int64_t m, int64_t n, int64_t k,
  * computation. */
 int64_t strassen_hybrid_workspace_size(int64_t m, int64_t n, int64_t k);
 
+/* One-level Strassen with the operand sums formed first (the Two-Level
+ * Strassen's Algorithm section's hybrid idea applied at one level): every
+ * two-term operand sum of eq. "gpu_allops" (five of A, five of B) is written
+ * once into caller workspace by one streaming pass per operand that reads
+ * each quadrant once; then each of the seven products runs the single-term
+ * kernel on the formed sums or the quadrants themselves and scatters its
+ * accumulator with signs into its C blocks, as in strassen_gemm_ex at
+ * levels = 1, so C needs no workspace.  The sums are formed in the same
+ * order and precision as the fused kernels form them (fp32 from the stored
+ * values, 16-bit data rounded once) and the products accumulate in the same
+ * order, so the result equals strassen_gemm_ex's one-level result bit for
+ * bit.  Worth it where staging multi-term sums inside the product kernel is
+ * the bottleneck (the BF16X3 mode).  A and B as stored (no transposes);
+ * a_type == b_type; modes and types as in strassen_gemm_ex; same degenerate
+ * cases.
+ * workspace: device memory of at least strassen_formed_workspace_size()
+ * bytes, 16-byte aligned, overlapping none of A, B, C; owned by the caller,
+ * contents undefined after the call; may be NULL when the product term is
+ * absent (m, n or k = 0, or alpha = 0).  Calls that overlap on one workspace
+ * race.  Enqueued on hip_stream (NULL = the null stream).
+ * Argument indices: m=1 n=2 k=3 A=4 lda=5 a_type=6 B=7 ldb=8 b_type=9 C=10
+ * ldc=11 alpha=12 beta=13 mode=14 workspace=15 workspace_bytes=16
+ * hip_stream=17.  Overlap of A or B with C reports -10. */
+int strassen_gemm_formed(int64_t m, int64_t n, int64_t k,
+                         const void *A, int64_t lda, strassen_dtype_t a_type,
+                         const void *B, int64_t ldb, strassen_dtype_t b_type,
+                         float *C, int64_t ldc,
+                         float alpha, float beta, strassen_mode_t mode,
+                         void *workspace, int64_t workspace_bytes, void *hip_stream);
+
+/* Workspace bytes strassen_gemm_formed needs: e * (5 sm sk + 5 sk sn) with
+ * the one-level block extents sm = ceil(m/2), sk = ceil(k/2), sn = ceil(n/2)
+ * (sk and sn rounded up to the 16-byte vector width: 4 fp32 or 8 16-bit
+ * elements) and e = 2 bytes for bf16/fp16 data, 4 for fp32 data in either
+ * mode; about 1.25 (mk + kn) e bytes.  Returns the size, or a negative
+ * argument index (m=1 n=2 k=3 dtype=4 mode=5).  Pure host computation. */
+int64_t strassen_formed_workspace_size(int64_t m, int64_t n, int64_t k,
+                                       strassen_dtype_t dtype, strassen_mode_t mode);
+
 /* Sets the stream strassen_gemm uses on the calling thread (a hipStream_t;
  * NULL = the null stream).  Always returns 0. */
 int strassen_set_stream(void *hip_stream);
@@ -139,8 +178,8 @@ int strassen_set_stream(void *hip_stream);
  * two per CU; per-wave costs fitted to MI355X measurements); for 16-bit
  * operands, 256x256 when every product of the launch has at least 128 such
  * tiles and the launch at least 256, else 128x128.  The others force one
- * shape for every launch (tuning, tests).  Process-wide; returns 0 or -1
- * (bad value). */
+ * shape for every launch (tuning, tests).  Applies to the calling thread's
+ * later calls only (like the stream); returns 0 or -1 (bad value). */
 #define STRASSEN_TILE_AUTO 0
 #define STRASSEN_TILE_128 1
 #define STRASSEN_TILE_256 2
@@ -155,8 +194,12 @@ int strassen_set_tile(int tile);
  *   (element-wise atomic update).  Fewer, fuller launches for small problems;
  *   the order of the additions varies, so results vary in the last bits.
  *   Applies to fp32 operands as stored (mode PLAIN, no transposes) at levels
- *   >= 1; other calls keep the batched schedule.
- * Process-wide; returns 0 or -1 (bad value). */
+ *   >= 1; other calls keep the batched schedule.  The atomics are the
+ *   hardware fp32 atomic add, which needs C in ordinary (coarse-grained)
+ *   device memory: with C in fine-grained or host-coherent memory the
+ *   concurrent schedule is not supported.
+ * Applies to the calling thread's later calls only; returns 0 or -1 (bad
+ * value). */
 #define STRASSEN_SCHEDULE_BATCHED 0
 #define STRASSEN_SCHEDULE_CONCURRENT 1
 int strassen_set_schedule(int schedule);

@@ -71,6 +71,9 @@ SIGNATURES = {
     "strassen_gemm_hybrid": (_int, [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _f32, _f32,
                                     _vp, _i64, _vp]),
     "strassen_hybrid_workspace_size": (_i64, [_i64, _i64, _i64]),
+    "strassen_gemm_formed": (_int, [_i64, _i64, _i64, _vp, _i64, _int, _vp, _i64, _int, _vp, _i64,
+                                    _f32, _f32, _int, _vp, _i64, _vp]),
+    "strassen_formed_workspace_size": (_i64, [_i64, _i64, _i64, _int, _int]),
     "strassen_set_stream": (_int, [_vp]),
     "strassen_set_tile": (_int, [_int]),
     "strassen_set_schedule": (_int, [_int]),
@@ -150,6 +153,16 @@ def strassen_gemm_hybrid(m, n, k, A, lda, B, ldb, C, ldc, alpha, beta, workspace
 
 def strassen_hybrid_workspace_size(m, n, k):
     return lib.strassen_hybrid_workspace_size(m, n, k)
+
+
+def strassen_gemm_formed(m, n, k, A, lda, a_type, B, ldb, b_type, C, ldc, alpha, beta, mode,
+                         workspace, workspace_bytes, hip_stream):
+    return lib.strassen_gemm_formed(m, n, k, A, lda, a_type, B, ldb, b_type, C, ldc, alpha, beta,
+                                    mode, workspace, workspace_bytes, hip_stream)
+
+
+def strassen_formed_workspace_size(m, n, k, dtype=STRASSEN_F32, mode=STRASSEN_MODE_PLAIN):
+    return lib.strassen_formed_workspace_size(m, n, k, dtype, mode)
 
 
 def strassen_set_stream(hip_stream):

@@ -90,3 +90,47 @@ def gemm_hybrid(A, B_, C, alpha=1.0, beta=1.0, workspace=None, stream=None):
     if rc != 0:
         raise B.StrassenError(rc, "strassen_gemm_hybrid")
     return C
+
+
+def formed_workspace_bytes(m, n, k, dtype=torch.float32, mode="plain"):
+    """Bytes of workspace gemm_formed needs for this shape, dtype and mode."""
+    need = B.strassen_formed_workspace_size(m, n, k, _DTYPES[dtype], _MODES[mode])
+    if need < 0:
+        raise B.StrassenError(int(need), "strassen_formed_workspace_size")
+    return need
+
+
+def gemm_formed(A, B_, C, alpha=1.0, beta=1.0, mode="plain", workspace=None, stream=None):
+    """One-level Strassen with the two-term operand sums formed first into
+    workspace: C := alpha * A @ B + beta * C in place, bit-identical to
+    gemm(..., levels=1).  A, B: fp32, bf16 or fp16 GPU tensors of one dtype,
+    as stored (no transposes); C fp32.  `workspace` is a GPU tensor of at
+    least formed_workspace_bytes(...) bytes (allocated by torch here when not
+    given: the library itself allocates nothing).  Returns C."""
+    if not (A.is_cuda and B_.is_cuda and C.is_cuda):
+        raise ValueError("A, B and C must be GPU tensors")
+    if A.dtype not in _DTYPES or B_.dtype != A.dtype:
+        raise TypeError("A and B must share a dtype among float32, bfloat16, float16")
+    if C.dtype != torch.float32:
+        raise TypeError("C must be float32")
+    if mode not in _MODES:
+        raise ValueError("mode must be one of %s" % sorted(_MODES))
+    m, k = A.shape
+    kb, n = B_.shape
+    if kb != k or tuple(C.shape) != (m, n):
+        raise ValueError("shape mismatch: A %s, B %s, C %s" % (tuple(A.shape), tuple(B_.shape), tuple(C.shape)))
+    need = formed_workspace_bytes(m, n, k, A.dtype, mode)
+    if workspace is None:
+        workspace = torch.empty(max(need, 16), dtype=torch.uint8, device=C.device)
+    wbytes = workspace.numel() * workspace.element_size()
+    if wbytes < need:
+        raise ValueError("workspace smaller than %d bytes" % need)
+    with torch.cuda.device(C.device):
+        s = stream if stream is not None else torch.cuda.current_stream(C.device)
+        rc = B.strassen_gemm_formed(m, n, k, A.data_ptr(), _ld(A, "A"), _DTYPES[A.dtype],
+                                    B_.data_ptr(), _ld(B_, "B"), _DTYPES[A.dtype],
+                                    C.data_ptr(), _ld(C, "C"), float(alpha), float(beta),
+                                    _MODES[mode], workspace.data_ptr(), wbytes, s.cuda_stream)
+    if rc != 0:
+        raise B.StrassenError(rc, "strassen_gemm_formed")
+    return C

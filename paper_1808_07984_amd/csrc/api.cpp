@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "kernel_args.hpp"
@@ -143,14 +144,15 @@ TermArg term(int64_t off, int64_t rows, int64_t cols, int sign, bool first) {
 }
 
 // Tile choice of the product kernels (strassen_set_tile): automatic, or
-// forced to 128x128 / 256x256 for tuning and testing.
-std::atomic<int> g_tile{STRASSEN_TILE_AUTO};
+// forced to 128x128 / 256x256 for tuning and testing.  Per calling thread,
+// like the stream, so concurrent callers do not change each other's calls.
+thread_local int g_tile = STRASSEN_TILE_AUTO;
 
-// Schedule of the products (strassen_set_schedule).
-std::atomic<int> g_schedule{STRASSEN_SCHEDULE_BATCHED};
+// Schedule of the products (strassen_set_schedule), per calling thread.
+thread_local int g_schedule = STRASSEN_SCHEDULE_BATCHED;
 
 bool use_large(int64_t sm, int64_t sn, int64_t sk, int batch, bool f32) {
-    const int mode = g_tile.load(std::memory_order_relaxed);
+    const int mode = g_tile;
     if (mode == STRASSEN_TILE_128) return false;
     if (mode == STRASSEN_TILE_256) return true;
     const int64_t per_product = ((sm + 255) / 256) * ((sn + 255) / 256);
@@ -323,7 +325,7 @@ int run(const Call &c) {
     const bool vec = (c.lda % fam.vec == 0) && (c.ldb % fam.vec == 0) &&
                      ((uintptr_t)c.A % 16 == 0) && ((uintptr_t)c.B % 16 == 0);
 
-    if (g_schedule.load(std::memory_order_relaxed) == STRASSEN_SCHEDULE_CONCURRENT && !fam.m16 &&
+    if (g_schedule == STRASSEN_SCHEDULE_CONCURRENT && !fam.m16 &&
         !c.trans_a && !c.trans_b && c.levels > 0)
         return run_concurrent(c, plan, vec);
 
@@ -560,6 +562,264 @@ int run_hybrid(const Call &c, float *ws) {
     return 0;
 }
 
+// ---------------------------------------------------------------------------
+// One-level "formed" schedule (the Two-Level section's hybrid idea applied at
+// the one level itself): every two-term operand sum of the seven products of
+// eq. gpu_allops (five of A, five of B) is written once into caller
+// workspace by one streaming pass per operand, which reads each quadrant
+// once; each product then runs the single-term kernel, A and B read from the
+// workspace or straight from the quadrant, and its accumulator is scattered
+// with signs into its C blocks as in the fused schedule, so C needs no
+// workspace.  The sums are formed in the fused kernels' order and precision
+// (fp32 from the stored values, the first term's sign factored out, 16-bit
+// data rounded once), and the product kernels accumulate in the same k
+// order, so the result equals the fused one-level result bit for bit.
+// ---------------------------------------------------------------------------
+struct FormedSum {
+    int nterms;
+    strassen::Term t[2];  // t[0].sign = +1; t[1].sign relative to the first
+};
+
+struct FormedGeom {
+    Plan plan;                            // one-level plan (block extents)
+    std::vector<FormedSum> asums, bsums;  // distinct multi-term operands
+    std::vector<int> a_of, b_of;          // per product: its sum, or -1
+    size_t es = 4;                        // bytes per workspace element
+    int64_t a_bytes = 0, bytes = 0;
+};
+
+int find_or_add(std::vector<FormedSum> &sums, const strassen::Term *t, int n) {
+    FormedSum f;
+    f.nterms = n;
+    for (int i = 0; i < n; ++i) f.t[i] = strassen::Term{t[i].block, t[i].sign * t[0].sign};
+    for (size_t j = 0; j < sums.size(); ++j) {
+        bool same = sums[j].nterms == n;
+        for (int i = 0; i < n && same; ++i)
+            same = sums[j].t[i].block == f.t[i].block && sums[j].t[i].sign == f.t[i].sign;
+        if (same) return (int)j;
+    }
+    sums.push_back(f);
+    return (int)sums.size() - 1;
+}
+
+FormedGeom formed_geom(int64_t m, int64_t n, int64_t k, const Family &fam) {
+    FormedGeom g;
+    g.plan = strassen::make_plan(m, n, k, 1, fam.vec);
+    for (const strassen::Product &p : g.plan.products) {
+        if (p.na > 2 || p.nb > 2) throw std::bad_alloc();  // one level: at most two terms
+        g.a_of.push_back(p.na > 1 ? find_or_add(g.asums, p.a, p.na) : -1);
+        g.b_of.push_back(p.nb > 1 ? find_or_add(g.bsums, p.b, p.nb) : -1);
+    }
+    g.es = (fam.m16 && fam.op != strassen::Operand16::kBf16x3) ? 2 : 4;
+    const Plan &pl = g.plan;
+    g.a_bytes = (int64_t)g.es * (int64_t)g.asums.size() * pl.sm * pl.sk;
+    g.bytes = g.a_bytes + (int64_t)g.es * (int64_t)g.bsums.size() * pl.sk * pl.sn;
+    return g;
+}
+
+// Starts the launch record of one kernel when recording is on.
+int record_begin(hipStream_t s, hipEvent_t *e0, hipEvent_t *e1, bool *timed) {
+    Recorder &rec = recorder();
+    *timed = false;
+    {
+        std::lock_guard<std::mutex> lk(rec.mu);
+        if (!rec.on) return 0;
+        hipError_t e = rec.take(e0);
+        if (e == hipSuccess) e = rec.take(e1);
+        if (e != hipSuccess) return (int)e;
+    }
+    *timed = true;
+    return (int)hipEventRecord(*e0, s);
+}
+
+int record_end(hipStream_t s, hipEvent_t e0, hipEvent_t e1, const char *kernel, int launch, int batch,
+               int workgroups, double flops) {
+    const hipError_t err = hipEventRecord(e1, s);
+    if (err != hipSuccess) return (int)err;
+    Record r;
+    std::memset(&r.info, 0, sizeof(r.info));
+    std::snprintf(r.info.kernel, sizeof(r.info.kernel), "%s", kernel);
+    r.info.launch = launch;
+    r.info.batch = batch;
+    r.info.workgroups = workgroups;
+    r.info.flops = flops;
+    r.e0 = e0;
+    r.e1 = e1;
+    Recorder &rec = recorder();
+    std::lock_guard<std::mutex> lk(rec.mu);
+    rec.recs.push_back(r);
+    ++rec.total;
+    return 0;
+}
+
+// Forms the sums of one operand X (quadrant (R, Cc) at X + R*srows*ldx +
+// Cc*scols, extents clipped to xr x xc) into `out`, one srows x scols block
+// per sum, dense with leading dimension scols.
+int form_operand(const std::vector<FormedSum> &sums, strassen::FormElem fe, size_t es, const void *X,
+                 int64_t ldx, int64_t xr, int64_t xc, int64_t srows, int64_t scols, char *out,
+                 bool vec, hipStream_t s, int launch) {
+    if (sums.empty()) return 0;
+    strassen::FormSource src[strassen::kFormMaxSources];
+    int blocks[strassen::kFormMaxSources];
+    int nsrc = 0;
+    auto source_of = [&](int block) {
+        for (int q = 0; q < nsrc; ++q)
+            if (blocks[q] == block) return q;
+        const int R = block / 2, Cc = block % 2;
+        blocks[nsrc] = block;
+        src[nsrc].ptr = static_cast<const char *>(X) + ((uint64_t)R * srows * ldx + (uint64_t)Cc * scols) * es;
+        src[nsrc].rows = (int32_t)strassen::block_extent(xr, srows, R);
+        src[nsrc].cols = (int32_t)strassen::block_extent(xc, scols, Cc);
+        return nsrc++;
+    };
+    strassen::FormOut o[strassen::kFormMaxOutputs];
+    if ((int)sums.size() > strassen::kFormMaxOutputs) return (int)hipErrorInvalidValue;
+    for (size_t i = 0; i < sums.size(); ++i) {
+        o[i].ptr = out + (uint64_t)i * srows * scols * es;
+        o[i].t0 = source_of(sums[i].t[0].block);
+        o[i].t1 = sums[i].nterms > 1 ? source_of(sums[i].t[1].block) : -1;
+        o[i].s1 = sums[i].nterms > 1 ? (float)sums[i].t[1].sign : 0.f;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool timed = false;
+    int rc = record_begin(s, &e0, &e1, &timed);
+    if (rc != 0) return rc;
+    const hipError_t err = strassen::launch_form_sums(fe, src, nsrc, ldx, o, (int)sums.size(), scols,
+                                                      srows, scols, vec, s);
+    if (err != hipSuccess) return (int)err;
+    if (timed)
+        return record_end(s, e0, e1, fe == strassen::FormElem::kF32 ? "form_sums<f32>" : "form_sums<16-bit>",
+                          launch, (int)sums.size(), (int)(srows < 65536 ? srows : 65536), 0.0);
+    return 0;
+}
+
+int run_formed(const Call &c, void *ws) {
+    if (c.m == 0 || c.n == 0) return 0;
+    if (c.k == 0 || c.alpha == 0.f)
+        return (int)strassen::launch_scale(c.C, c.ldc, c.m, c.n, c.beta, c.stream);
+    const Family fam = family(c.a_type, c.mode);
+    const FormedGeom g = formed_geom(c.m, c.n, c.k, fam);
+    const Plan &plan = g.plan;
+    const int64_t sm = plan.sm, sn = plan.sn, sk = plan.sk;
+    const size_t in_es = elem_size(c.a_type);
+    char *wa = static_cast<char *>(ws);
+    char *wb = wa + g.a_bytes;
+    const strassen::FormElem fe = g.es == 4                       ? strassen::FormElem::kF32
+                                  : c.a_type == STRASSEN_BF16 ? strassen::FormElem::kBf16
+                                                              : strassen::FormElem::kF16;
+    const bool vec_a = (c.lda % fam.vec == 0) && ((uintptr_t)c.A % 16 == 0);
+    const bool vec_b = (c.ldb % fam.vec == 0) && ((uintptr_t)c.B % 16 == 0);
+    int rc = form_operand(g.asums, fe, in_es, c.A, c.lda, c.m, c.k, sm, sk, wa, vec_a, c.stream, 0);
+    if (rc != 0) return rc;
+    rc = form_operand(g.bsums, fe, in_es, c.B, c.ldb, c.k, c.n, sk, sn, wb, vec_b, c.stream, 1);
+    if (rc != 0) return rc;
+
+    // Products, batch by batch in the plan's order; a batch whose products
+    // take an operand from different places is split by source.
+    int launch = 2;
+    for (const strassen::Batch &bt : plan.batches) {
+        for (int pass = 0; pass < 4; ++pass) {
+            const bool fa = (pass & 1) != 0, fb = (pass & 2) != 0;
+            std::vector<int> sel;
+            for (int pi : bt.products)
+                if ((g.a_of[pi] >= 0) == fa && (g.b_of[pi] >= 0) == fb) sel.push_back(pi);
+            if (sel.empty()) continue;
+            LaunchArgs a;
+            std::memset(&a, 0, sizeof(a));
+            a.A = fa ? static_cast<const void *>(wa) : c.A;
+            a.B = fb ? static_cast<const void *>(wb) : c.B;
+            a.C = c.C;
+            a.lda = fa ? sk : c.lda;
+            a.ldb = fb ? sn : c.ldb;
+            a.ldc = c.ldc;
+            a.sm = (int32_t)sm;
+            a.sn = (int32_t)sn;
+            a.sk = (int32_t)sk;
+            a.alpha = c.alpha;
+            a.beta = c.beta;
+            const int batch = (int)sel.size();
+            const bool large = use_large(sm, sn, sk, batch, !fam.m16);
+            const strassen::KernelShape ks = shape_of(fam, large, 1, 1, bt.wc, true);
+            a.tiles_m = (int32_t)((sm + ks.mt - 1) / ks.mt);
+            a.tiles_n = (int32_t)((sn + ks.nt - 1) / ks.nt);
+            for (int z = 0; z < batch; ++z) {
+                const int pi = sel[z];
+                const strassen::Product &p = plan.products[pi];
+                ProductArg &pa = a.prod[z];
+                pa.na = 1;
+                pa.nb = 1;
+                pa.nc = p.nc;
+                if (fa) {
+                    int64_t rows = 0, cols = 0;
+                    for (int t = 0; t < p.na; ++t) {
+                        rows = std::max(rows, strassen::block_extent(c.m, sm, p.a[t].block / 2));
+                        cols = std::max(cols, strassen::block_extent(c.k, sk, p.a[t].block % 2));
+                    }
+                    pa.a[0] = term((int64_t)g.a_of[pi] * sm * sk, rows, cols, p.a[0].sign, false);
+                } else {
+                    const int R = p.a[0].block / 2, Cc = p.a[0].block % 2;
+                    pa.a[0] = term(R * sm * c.lda + Cc * sk, strassen::block_extent(c.m, sm, R),
+                                   strassen::block_extent(c.k, sk, Cc), p.a[0].sign, false);
+                }
+                if (fb) {
+                    int64_t rows = 0, cols = 0;
+                    for (int t = 0; t < p.nb; ++t) {
+                        rows = std::max(rows, strassen::block_extent(c.k, sk, p.b[t].block / 2));
+                        cols = std::max(cols, strassen::block_extent(c.n, sn, p.b[t].block % 2));
+                    }
+                    pa.b[0] = term((int64_t)g.b_of[pi] * sk * sn, rows, cols, p.b[0].sign, false);
+                } else {
+                    const int R = p.b[0].block / 2, Cc = p.b[0].block % 2;
+                    pa.b[0] = term(R * sk * c.ldb + Cc * sn, strassen::block_extent(c.k, sk, R),
+                                   strassen::block_extent(c.n, sn, Cc), p.b[0].sign, false);
+                }
+                for (int t = 0; t < p.nc; ++t) {
+                    const int R = p.c[t].block / 2, Cc = p.c[t].block % 2;
+                    pa.c[t] = term(R * sm * c.ldc + Cc * sn, strassen::block_extent(c.m, sm, R),
+                                   strassen::block_extent(c.n, sn, Cc), p.c[t].sign, p.c_first[t]);
+                }
+            }
+            const bool vec = (fa || vec_a) && (fb || vec_b);
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            bool timed = false;
+            rc = record_begin(c.stream, &e0, &e1, &timed);
+            if (rc != 0) return rc;
+            const hipError_t err =
+                fam.m16 ? strassen::launch_m16(fam.op, false, false, large, 1, 1, bt.wc, a, batch, vec, c.stream)
+                        : strassen::launch_f32(false, false, large, 1, 1, bt.wc, a, batch, vec, c.stream);
+            if (err != hipSuccess) return (int)err;
+            if (timed) {
+                char name[64];
+                std::snprintf(name, sizeof(name), "%s<1,1,%d,%s>",
+                              fam.m16 ? strassen::m16_kernel_name(fam.op, large) : strassen::f32_kernel_name(large),
+                              bt.wc, vec ? "vec" : "scalar");
+                rc = record_end(c.stream, e0, e1, name, launch, batch, a.tiles_m * a.tiles_n * batch,
+                                2.0 * (double)batch * (double)sm * (double)sn * (double)sk);
+                if (rc != 0) return rc;
+            }
+            ++launch;
+        }
+    }
+    return 0;
+}
+
+// Maps a strassen_gemm_ex argument index to its strassen_gemm_formed position
+// (levels and the transpose flags cannot be wrong there).
+int to_formed_index(int code) {
+    switch (-code) {
+        case 7: case 11: case 16: return -1;  // not reachable
+        case 8: return -7;
+        case 9: return -8;
+        case 10: return -9;
+        case 12: return -10;
+        case 13: return -11;
+        case 14: return -12;
+        case 15: return -13;
+        case 17: return -14;
+        default: return code;
+    }
+}
+
 // Maps a strassen_gemm_ex argument index to its strassen_gemm position.
 int to_base_index(int code) {
     switch (-code) {
@@ -656,6 +916,48 @@ int strassen_gemm_hybrid(int64_t m, int64_t n, int64_t k, const float *A, int64_
     }
 }
 
+int64_t strassen_formed_workspace_size(int64_t m, int64_t n, int64_t k, strassen_dtype_t dtype,
+                                       strassen_mode_t mode) {
+    if (m < 0 || m >= kMaxDim) return -1;
+    if (n < 0 || n >= kMaxDim) return -2;
+    if (k < 0 || k >= kMaxDim) return -3;
+    if (!valid_dtype(dtype)) return -4;
+    if (mode != STRASSEN_MODE_PLAIN && mode != STRASSEN_MODE_BF16X3) return -5;
+    if (mode == STRASSEN_MODE_BF16X3 && dtype != STRASSEN_F32) return -5;
+    try {
+        return formed_geom(m, n, k, family(dtype, mode)).bytes;
+    } catch (...) {
+        return -(int64_t)hipErrorOutOfMemory;
+    }
+}
+
+int strassen_gemm_formed(int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
+                         strassen_dtype_t a_type, const void *B, int64_t ldb, strassen_dtype_t b_type,
+                         float *C, int64_t ldc, float alpha, float beta, strassen_mode_t mode,
+                         void *workspace, int64_t workspace_bytes, void *hip_stream) {
+    const Call c{m, n, k, A, lda, a_type, 0, B, ldb, b_type, 0, C, ldc,
+                 alpha, beta, 1, mode, (hipStream_t)hip_stream};
+    const int v = validate(c);
+    if (v != 0) return to_formed_index(v);
+    const bool product = m > 0 && n > 0 && k > 0 && alpha != 0.f;
+    try {
+        if (!product) return run_formed(c, nullptr);
+        const int64_t need = strassen_formed_workspace_size(m, n, k, a_type, mode);
+        if (need < 0) return (int)(-need);
+        if (workspace == nullptr || (uintptr_t)workspace % 16 != 0) return -15;
+        if (workspace_bytes < need) return -16;
+        const uint64_t wbytes = (uint64_t)need;
+        const size_t es = elem_size(a_type);
+        if (overlap(workspace, wbytes, A, span_bytes(m, k, lda, es)) ||
+            overlap(workspace, wbytes, B, span_bytes(k, n, ldb, es)) ||
+            overlap(workspace, wbytes, C, span_bytes(m, n, ldc, 4)))
+            return -15;
+        return run_formed(c, workspace);
+    } catch (...) {
+        return (int)hipErrorOutOfMemory;
+    }
+}
+
 int strassen_set_stream(void *hip_stream) {
     g_stream = (hipStream_t)hip_stream;
     return 0;
@@ -664,14 +966,14 @@ int strassen_set_stream(void *hip_stream) {
 int strassen_set_schedule(int schedule) {
     if (schedule != STRASSEN_SCHEDULE_BATCHED && schedule != STRASSEN_SCHEDULE_CONCURRENT)
         return -1;
-    g_schedule.store(schedule, std::memory_order_relaxed);
+    g_schedule = schedule;
     return 0;
 }
 
 int strassen_set_tile(int tile) {
     if (tile != STRASSEN_TILE_AUTO && tile != STRASSEN_TILE_128 && tile != STRASSEN_TILE_256)
         return -1;
-    g_tile.store(tile, std::memory_order_relaxed);
+    g_tile = tile;
     return 0;
 }
 

@@ -5,6 +5,8 @@
 // read once and the sum written once, in 16-byte vectors where aligned.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+
 #include "launch.hpp"
 
 namespace strassen {
@@ -52,6 +54,103 @@ __global__ __launch_bounds__(256) void form_kernel(const FormArgs a) {
     }
 }
 
+// Operand sums of the one-level "formed" schedule: every signed sum of two
+// quadrants that a product needs is written once into workspace by one
+// streaming pass per operand, which reads each quadrant once:
+//     out_o[r][c] = x_{t0}[r][c] + s1_o * x_{t1}[r][c]      (t1 < 0: x_{t0})
+// summed in fp32 from the stored values and, for 16-bit data, rounded once to
+// nearest even, exactly as the fused kernels stage the same sum (eq.
+// straprim1 with the first term's sign factored out).  A source element
+// outside its quadrant's extent is a virtual zero ("Handling the Fringes").
+// One row of the output block per workgroup step; each thread handles one
+// 16-byte unit per source and output.
+struct SumsArgs {
+    FormSource src[kFormMaxSources];
+    FormOut out[kFormMaxOutputs];
+    int32_t nsrc, nout;
+    int64_t ld_src, ld_out;
+    int64_t rows, cols;  // output block extent, cols a multiple of the unit
+};
+
+template <FormElem E>
+struct Elem;
+template <>
+struct Elem<FormElem::kF32> {
+    static constexpr int NV = 4;
+    using In = float;
+    __device__ static float get(float x) { return x; }
+    __device__ static float put(float x) { return x; }
+};
+template <>
+struct Elem<FormElem::kBf16> {
+    static constexpr int NV = 8;
+    using In = unsigned short;
+    __device__ static float get(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+    __device__ static unsigned short put(float x) { return __builtin_bit_cast(unsigned short, (__bf16)x); }
+};
+template <>
+struct Elem<FormElem::kF16> {
+    static constexpr int NV = 8;
+    using In = unsigned short;
+    __device__ static float get(unsigned short h) { return (float)__builtin_bit_cast(_Float16, h); }
+    __device__ static unsigned short put(float x) { return __builtin_bit_cast(unsigned short, (_Float16)x); }
+};
+
+template <FormElem E, bool VEC>
+__global__ __launch_bounds__(256) void form_sums_kernel(const SumsArgs a) {
+    using T = Elem<E>;
+    using In = typename T::In;
+    constexpr int NV = T::NV;
+    typedef In Vec __attribute__((ext_vector_type(NV)));
+    const int64_t units = a.cols / NV;
+    for (int64_t r = blockIdx.x; r < a.rows; r += gridDim.x) {
+        for (int64_t u = threadIdx.x; u < units; u += blockDim.x) {
+            const int64_t c = u * NV;
+            float x[kFormMaxSources][NV];
+#pragma unroll
+            for (int q = 0; q < kFormMaxSources; ++q) {
+#pragma unroll
+                for (int e = 0; e < NV; ++e) x[q][e] = 0.f;
+                if (q >= a.nsrc) continue;
+                const FormSource sq = a.src[q];
+                if (r >= sq.rows) continue;
+                const In *p = static_cast<const In *>(sq.ptr) + r * a.ld_src + c;
+                if (VEC && c + NV <= sq.cols) {
+                    const Vec v = *reinterpret_cast<const Vec *>(p);
+#pragma unroll
+                    for (int e = 0; e < NV; ++e) x[q][e] = T::get(v[e]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < NV; ++e)
+                        if (c + e < sq.cols) x[q][e] = T::get(p[e]);
+                }
+            }
+#pragma unroll
+            for (int o = 0; o < kFormMaxOutputs; ++o) {
+                if (o >= a.nout) break;
+                const FormOut fo = a.out[o];
+                Vec v;
+#pragma unroll
+                for (int e = 0; e < NV; ++e) {
+                    float s = 0.f;
+#pragma unroll
+                    for (int q = 0; q < kFormMaxSources; ++q)
+                        if (q == fo.t0) s = x[q][e];
+                    if (fo.t1 >= 0) {
+                        float y = 0.f;
+#pragma unroll
+                        for (int q = 0; q < kFormMaxSources; ++q)
+                            if (q == fo.t1) y = x[q][e];
+                        s = __builtin_fmaf(fo.s1, y, s);
+                    }
+                    v[e] = T::put(s);
+                }
+                *reinterpret_cast<Vec *>(static_cast<In *>(fo.ptr) + r * a.ld_out + c) = v;
+            }
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_form(float *out, int64_t ld_out, int64_t rows, int64_t cols, int64_t ld_src,
@@ -73,6 +172,48 @@ hipError_t launch_form(float *out, int64_t ld_out, int64_t rows, int64_t cols, i
         hipLaunchKernelGGL(form_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL(form_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace strassen
+
+namespace strassen {
+
+hipError_t launch_form_sums(FormElem elem, const FormSource *src, int nsrc, int64_t ld_src,
+                            const FormOut *out, int nout, int64_t ld_out, int64_t rows, int64_t cols,
+                            bool vec, hipStream_t s) {
+    const int nv = elem == FormElem::kF32 ? 4 : 8;
+    if (nsrc < 1 || nsrc > kFormMaxSources || nout < 1 || nout > kFormMaxOutputs || cols % nv != 0 ||
+        ld_out % nv != 0 || rows < 0)
+        return hipErrorInvalidValue;
+    for (int o = 0; o < nout; ++o)
+        if (out[o].t0 < 0 || out[o].t0 >= nsrc || out[o].t1 >= nsrc) return hipErrorInvalidValue;
+    if (rows == 0 || cols == 0) return hipSuccess;
+    SumsArgs a;
+    std::memset(&a, 0, sizeof(a));
+    for (int q = 0; q < nsrc; ++q) a.src[q] = src[q];
+    for (int o = 0; o < nout; ++o) a.out[o] = out[o];
+    a.nsrc = nsrc;
+    a.nout = nout;
+    a.ld_src = ld_src;
+    a.ld_out = ld_out;
+    a.rows = rows;
+    a.cols = cols;
+    const unsigned blocks = (unsigned)(rows < 65536 ? rows : 65536);
+    switch (elem) {
+        case FormElem::kF32:
+            if (vec) hipLaunchKernelGGL((form_sums_kernel<FormElem::kF32, true>), dim3(blocks), dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((form_sums_kernel<FormElem::kF32, false>), dim3(blocks), dim3(256), 0, s, a);
+            break;
+        case FormElem::kBf16:
+            if (vec) hipLaunchKernelGGL((form_sums_kernel<FormElem::kBf16, true>), dim3(blocks), dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((form_sums_kernel<FormElem::kBf16, false>), dim3(blocks), dim3(256), 0, s, a);
+            break;
+        case FormElem::kF16:
+            if (vec) hipLaunchKernelGGL((form_sums_kernel<FormElem::kF16, true>), dim3(blocks), dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((form_sums_kernel<FormElem::kF16, false>), dim3(blocks), dim3(256), 0, s, a);
+            break;
+    }
     return hipGetLastError();
 }
 

@@ -310,6 +310,18 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
     // Used where W_A >= W_B and either both or neither operand is
     // transposed.
     constexpr bool kWeaveDeep = kDeep && Ops::kX3 && WA >= WB && A_KC != B_KC;
+    // Compensated products with A as stored and B summed: a 16-deep fp32
+    // k-tile makes A's rows 64 bytes, half a cache line, and the two-ahead
+    // loop requested the two halves of each line a trip apart, so the L2
+    // served every line of A twice.  Here A's loads of the two k-tiles of
+    // one trip pair are issued back to back (both halves of a line requested
+    // together) into one register set holding both tiles; B keeps its
+    // per-tile sets.  Measured -10 % for (2,2,x) and -3 to -4 % for (1,2,2)
+    // at 8192^3 per product, A/B in one process, bit-identical; (2,1,2)
+    // measured 1-2 % slower this way and keeps the per-tile loads; the
+    // two-level variants were not measured and keep them too.
+    constexpr bool kPairA = kDeep && Ops::kX3 && A_KC && !B_KC && WB == 2 && WC <= 2 && C::KT == 16 &&
+                            C::BM == 4 && SA::VECS == 2 && SA::LOADS == 1;
     // Buffer loads for single-term operands and the two-ahead loop (measured
     // faster there); otherwise plain global loads measured faster.
     constexpr bool kBufferLoads = WA + WB <= 2 || kDeep;
@@ -642,7 +654,128 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
 
     const int nk = (args.sk + C::KT - 1) / C::KT;
     int kt = 0;
-    if (kDeep && nfast >= 3) {
+    bool a_pairs_done = false;
+    if constexpr (kPairA) {
+        if (nfast >= 3) {
+            // Two-ahead loop with A's k-tiles loaded in pairs.  pa[t][2u + w]
+            // holds unit u of term t of tile kt0 + w (kt0 even); B's sets
+            // alternate, bq holding odd tiles and raw_b even ones.  At the
+            // top of a trip tile kt is in LDS buffer 0, tile kt + 1 in pa
+            // (w = 1) and bq.
+            a_pairs_done = true;
+            uint32_t pa_off[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                int x, k;
+                SA::coords(tid, p >> 1, x, k);
+                pa_off[p] = (uint32_t)sizeof(In) * ((uint32_t)x * (uint32_t)lda + (uint32_t)(k + C::KT * (p & 1)));
+            }
+            V pa[WA][4];
+            V bq[WB][SB::VECS][SB::LOADS];
+            constexpr int NPA = 4 * WA;
+            // loads [lo, hi) of A's pair of k-tiles kt0, kt0 + 1
+            auto load_pair = [&](int kt0, int lo, int hi) __attribute__((always_inline)) {
+#pragma unroll
+                for (int t = 0; t < WA; ++t) {
+                    const char *tb = reinterpret_cast<const char *>(A + P.a[t].off + a_org) + a_step * kt0;
+                    const auto r = raw_rsrc(tb);
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) {
+                        const int idx = t * 4 + p;
+                        if (idx >= lo && idx < hi) pa[t][p] = buffer_load16<V>(r, pa_off[p]);
+                    }
+                }
+            };
+            auto load_b = [&](auto &rb, int ktb, int lo, int hi) __attribute__((always_inline)) {
+                load_fast(rb, B, P.b, SB{}, std::integral_constant<int, WB>{}, b_off, b_org, b_step, ktb,
+                          lo, hi);
+            };
+            // A's signed sum of tile kt0 + w, split hi/lo, into LDS buffer buf
+            auto store_a = [&](int buf, int w) __attribute__((always_inline)) {
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    int x, k;
+                    SA::coords(tid, u, x, k);
+                    u16x4 wh, wl;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        float s = pa[0][2 * u + w][e];
+#pragma unroll
+                        for (int t = 1; t < WA; ++t) s += (P.a[t].sign * sa0) * pa[t][2 * u + w][e];
+                        wh[e] = Ops::from_f32(s);
+                        wl[e] = Ops::from_f32(s - Ops::bf16_to_f32(wh[e]));
+                    }
+                    const int off = x * SA::LDX + k;
+                    *reinterpret_cast<u16x4 *>(&As[buf][0][off]) = wh;
+                    *reinterpret_cast<u16x4 *>(&As[buf][1][off]) = wl;
+                }
+            };
+            // The MFMA rows of the k-tile in buffer buf, hook(g) before row g.
+            auto rows_hooked = [&](int buf, auto hook) __attribute__((always_inline)) {
+                u32x4 af[NPLANES][C::BM], bf[NPLANES][C::BN];
+#pragma unroll
+                for (int q = 0; q < NPLANES; ++q) {
+#pragma unroll
+                    for (int i = 0; i < C::BM; ++i)
+                        af[q][i] = frag(&As[buf][q][0], SA{}, wm * C::WM + i * 32 + l32, 8 * h);
+#pragma unroll
+                    for (int j = 0; j < C::BN; ++j)
+                        bf[q][j] = frag(&Bs[buf][q][0], SB{}, wn * C::WN + j * 32 + l32, 8 * h);
+                }
+#pragma unroll
+                for (int i = 0; i < C::BM; ++i) {
+                    hook(i);
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int j = 0; j < C::BN; ++j) {
+                        acc[i][j] = mfma(af[0][i], bf[0][j], acc[i][j]);
+                        acc[i][j] = mfma(af[0][i], bf[NPLANES - 1][j], acc[i][j]);
+                        acc[i][j] = mfma(af[NPLANES - 1][i], bf[0][j], acc[i][j]);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            };
+            load_pair(0, 0, NPA);
+            load_b(raw_b, 0, 0, NLB);
+            store_a(0, 0);
+            stage_store_from(0, raw_a, raw_b, 2);
+            load_b(bq, 1, 0, NLB);
+            __syncthreads();
+            for (; kt + 3 < nfast; kt += 2) {
+                // tile kt: store tile kt + 1 into buffer 1, load A's tiles
+                // kt + 2 and kt + 3 and B's tile kt + 2
+                rows_hooked(0, [&](int g) __attribute__((always_inline)) {
+                    if (g == 0) load_b(raw_b, kt + 2, 0, NLB / 2);
+                    if (g == 1) {
+                        store_a(1, 1);
+                        load_pair(kt + 2, 0, NPA / 2);
+                    }
+                    if (g == 2) {
+                        load_pair(kt + 2, NPA / 2, NPA);
+                        load_b(raw_b, kt + 2, NLB / 2, NLB);
+                    }
+                    if (g == 3) stage_store_from(1, raw_a, bq, 2);
+                });
+                __syncthreads();
+                // tile kt + 1: store tile kt + 2 into buffer 0, load B's tile kt + 3
+                rows_hooked(1, [&](int g) __attribute__((always_inline)) {
+                    if (g == 0) load_b(bq, kt + 3, 0, NLB / 2);
+                    if (g == 1) store_a(0, 0);
+                    if (g == 2) load_b(bq, kt + 3, NLB / 2, NLB);
+                    if (g == 3) stage_store_from(0, raw_a, raw_b, 2);
+                });
+                __syncthreads();
+            }
+            compute(0);
+            store_a(1, 1);
+            stage_store_from(1, raw_a, bq, 2);
+            __syncthreads();
+            kt += 1;
+        }
+    }
+    if (a_pairs_done) {
+        // the one-ahead loop below goes on from tile kt in buffer 1
+    } else if (kDeep && nfast >= 3) {
         // Two k-tiles per trip, the register sets alternating: tile kt is in
         // LDS buffer 0 and tile kt + 1 in raw_a/raw_b at the top of a trip.
         // The loop ends with tile kt in buffer 1; the loops below go on.
@@ -854,6 +987,11 @@ hipError_t dispatch(int wa, int wb, int wc, const LaunchArgs &a, int batch, bool
     STRASSEN_CASE(2, 2, 1)
     STRASSEN_CASE(1, 2, 2)
     STRASSEN_CASE(2, 1, 2)
+    // formed one-level schedule (operands as stored): single-term products
+    // with two outputs
+    if constexpr (A_KC && !B_KC) {
+        STRASSEN_CASE(1, 1, 2)
+    }
     STRASSEN_CASE(4, 4, 4)
     STRASSEN_CASE(1, 4, 4)
     STRASSEN_CASE(2, 4, 4)

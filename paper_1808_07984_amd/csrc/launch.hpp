@@ -67,6 +67,28 @@ struct FormTerm {
 hipError_t launch_form(float *out, int64_t ld_out, int64_t rows, int64_t cols, int64_t ld_src,
                        const FormTerm *terms, int nterms, bool vec, hipStream_t s);
 
+// One-level "formed" schedule: out_o = x_{t0} + s1_o * x_{t1} (t1 < 0: the
+// single term x_{t0}) over a rows x cols block, for up to five outputs from up
+// to four source quadrants sharing ld_src; sums in fp32 from the stored
+// element type, 16-bit outputs rounded once to nearest even; a source element
+// outside its rows x cols extent is zero.  Outputs are dense (ld_out), cols
+// and ld_out multiples of the 16-byte unit (4 fp32 or 8 16-bit elements),
+// 16-byte aligned; vec = sources aligned for 16-byte loads.
+enum class FormElem { kF32, kBf16, kF16 };
+constexpr int kFormMaxSources = 4, kFormMaxOutputs = 5;
+struct FormSource {
+    const void *ptr;
+    int32_t rows, cols;
+};
+struct FormOut {
+    void *ptr;
+    int32_t t0, t1;
+    float s1;
+};
+hipError_t launch_form_sums(FormElem elem, const FormSource *src, int nsrc, int64_t ld_src,
+                            const FormOut *out, int nout, int64_t ld_out, int64_t rows, int64_t cols,
+                            bool vec, hipStream_t s);
+
 // C := beta * C over an m x n matrix (beta == 0 writes zeros, C not read).
 hipError_t launch_scale(float *C, int64_t ldc, int64_t m, int64_t n, float beta, hipStream_t s);
 

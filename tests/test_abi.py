@@ -148,3 +148,57 @@ def test_hybrid_validation():
     assert call(wsb=need - 4) == -13
     assert call(ws=C + 64) == -12         # workspace overlaps C
     assert call(C=A + 128) == -8          # A overlaps C
+
+
+def test_formed_workspace_size():
+    # e * (5 sm sk + 5 sk sn), one-level extents, sk and sn rounded to the
+    # 16-byte vector width (4 fp32, 8 16-bit elements)
+    def want(m, n, k, e, v):
+        sm = -(-m // 2)
+        sk = -(-(-(-k // 2)) // v) * v
+        sn = -(-(-(-n // 2)) // v) * v
+        return e * (5 * sm * sk + 5 * sk * sn)
+    f = sg.strassen_formed_workspace_size
+    assert f(16384, 16384, 16384, sg.STRASSEN_F32, sg.STRASSEN_MODE_BF16X3) == 4 * 10 * 8192 * 8192
+    for (m, n, k) in ((15001, 17003, 9007), (3, 5, 7), (1, 1, 1), (3000, 20000, 5000)):
+        assert f(m, n, k, sg.STRASSEN_F32, sg.STRASSEN_MODE_PLAIN) == want(m, n, k, 4, 4)
+        assert f(m, n, k, sg.STRASSEN_F32, sg.STRASSEN_MODE_BF16X3) == want(m, n, k, 4, 4)
+        assert f(m, n, k, sg.STRASSEN_BF16, sg.STRASSEN_MODE_PLAIN) == want(m, n, k, 2, 8)
+        assert f(m, n, k, sg.STRASSEN_F16, sg.STRASSEN_MODE_PLAIN) == want(m, n, k, 2, 8)
+    assert f(-1, 1, 1, 0, 0) == -1
+    assert f(1, -1, 1, 0, 0) == -2
+    assert f(1, 1, -1, 0, 0) == -3
+    assert f(1, 1, 1, 7, 0) == -4
+    assert f(1, 1, 1, sg.STRASSEN_BF16, sg.STRASSEN_MODE_BF16X3) == -5
+
+
+def test_formed_validation():
+    need = sg.strassen_formed_workspace_size(64, 64, 64, 0, 0)
+    A, B, C, W = 1 << 20, 1 << 22, 1 << 24, 1 << 26
+    names = ["m", "n", "k", "A", "lda", "a_type", "B", "ldb", "b_type", "C", "ldc", "alpha",
+             "beta", "mode", "ws", "wsb", "stream"]
+    base = dict(zip(names, [64, 64, 64, A, 64, 0, B, 64, 0, C, 64, 1.0, 1.0, 0, W, need, None]))
+
+    def call(**kw):
+        return sg.strassen_gemm_formed(*dict(base, **kw).values())
+
+    assert call(m=-1) == -1
+    assert call(k=-1) == -3
+    assert call(A=None) == -4
+    assert call(lda=63) == -5
+    assert call(a_type=5) == -6
+    assert call(B=None) == -7
+    assert call(ldb=3) == -8
+    assert call(b_type=1) == -9
+    assert call(C=None) == -10
+    assert call(ldc=3) == -11
+    assert call(mode=4) == -14
+    assert call(mode=1, a_type=1, b_type=1) == -14
+    assert call(ws=None) == -15
+    assert call(ws=W + 8) == -15          # not 16-byte aligned
+    assert call(wsb=need - 1) == -16
+    assert call(ws=C + 256) == -15        # workspace overlaps C
+    assert call(ws=A - 64) == -15         # workspace overlaps A
+    assert call(C=A + 128) == -10         # A overlaps C
+    assert call(m=0, A=None, B=None, C=None, ws=None) == 0
+    assert call(n=0, A=None, B=None, C=None, ws=None) == 0
