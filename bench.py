@@ -13,10 +13,12 @@ kernel of the headline level, timed per launch with HIP events recorded by
 the library itself on the launch stream.  The CPU oracle is timed on a
 bounded sample of rows of the same product (cpu_baseline); it is used
 nowhere else here: the sampled error checks compare against fp64 dot
-products computed in this script.  Secondary sections: bf16 / fp16 /
-bf16x3 at 4096-16384 (N(0,1) and rows/columns scaled over six decades),
-differentiation, small sizes by schedule, and with --sweep the square and
-rank-k fp32 sweep and the awkward padded shapes.
+products computed in this script.  Secondary sections: the compensated
+bf16x3 mode at 8192^3 and 16384^3 (plain, fused one-level, formed one-level
+and two-level products timed in interleaved rounds), bf16 / fp16 / bf16x3 at
+4096-16384 (N(0,1) and rows/columns scaled over six decades), the fp32
+square and rank-k sweep and the awkward padded shapes, differentiation, and
+small sizes by schedule.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -51,43 +53,144 @@ def parse():
                    help="skip the bf16 / fp16 / bf16x3 section")
     p.add_argument("--no-autograd", action="store_true",
                    help="skip the forward + backward section")
-    p.add_argument("--sweep", action="store_true",
-                   help="also time the fp32 square / rank-k sweep and the awkward shapes (off by "
-                        "default: the rank-k launches share kernel and grid with the headline's, "
-                        "which would mix them in per-kernel profiles of the default run)")
+    p.add_argument("--no-sweep", action="store_true",
+                   help="skip the fp32 square / rank-k sweep and the awkward shapes (their "
+                        "rank-k launches share kernel and grid with the headline's, so per-kernel "
+                        "profiles of the headline are taken without them)")
+    p.add_argument("--no-compensated", action="store_true",
+                   help="skip the bf16x3 plain / fused / formed comparison")
     p.add_argument("--no-small", action="store_true",
                    help="skip the small-size schedule section")
     return p.parse_args()
 
 
+def host_cpu():
+    """Model name and core / thread counts of the host CPU."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    cores = set()
+    try:
+        with open("/proc/cpuinfo") as f:
+            phys = core = None
+            for ln in f:
+                if ln.startswith("physical id"):
+                    phys = ln.split(":", 1)[1].strip()
+                elif ln.startswith("core id"):
+                    core = ln.split(":", 1)[1].strip()
+                    cores.add((phys, core))
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(), "physical_cores": len(cores) or None,
+            "affinity_threads": len(os.sched_getaffinity(0)),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def _omp_set_threads(n):
+    """Sets the OpenMP thread count of the oracle library (libgomp, shared
+    with this process) and returns the previous count."""
+    import ctypes
+    gomp = ctypes.CDLL("libgomp.so.1")
+    prev = gomp.omp_get_max_threads()
+    gomp.omp_set_num_threads(int(n))
+    return prev
+
+
 def cpu_baseline(A, B, C, target_s):
-    """The oracle's classical fp64 GEMM on the first R rows of the product,
-    R sized for about target_s seconds; rate scaled to TFLOP/s."""
+    """The oracle on the GPU host's cores: its classical fp64 GEMM on the
+    first rows of the headline product (about target_s seconds; the `value`),
+    and, on bounded samples (leading rows, about a second each), the other
+    workload shapes: the small square, the square and rank-k sweep, the
+    awkward shapes; its fp64 Strassen recursion at one and two levels; and
+    the classical GEMM on one core.  Rates in TFLOP/s = 2 * rows * n * k / t."""
     import numpy as np
     import oracle
 
-    n, k = B.shape[1], A.shape[1]
-    Bd = oracle._f64(B)
+    lib = oracle._load()
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
 
-    def run(rows):
-        Ad = oracle._f64(A[:rows])
-        Cd = oracle._f64(C[:rows])
+    def classical(Ad, Bd, rows):
+        m, k = Ad.shape
+        n = Bd.shape[1]
+        Cd = np.zeros((rows, n))
         t0 = time.perf_counter()
-        oracle._load().oracle_gemm_f64(rows, n, k, oracle._ptr(Ad), k, oracle._ptr(Bd), n,
-                                       oracle._ptr(Cd), n, 1.0, 1.0)
+        lib.oracle_gemm_f64(rows, n, k, oracle._ptr(Ad), k, oracle._ptr(Bd), n, oracle._ptr(Cd), n,
+                            1.0, 0.0)
         return time.perf_counter() - t0
 
-    probe = max(threads, 4)
-    t = run(probe)
-    rows = int(min(A.shape[0], max(probe, probe * target_s / max(t, 1e-6))))
-    rows = max(threads, (rows // threads) * threads)
-    t = run(rows)
-    flops = 2.0 * rows * n * k
-    del np
-    return {"value": flops / t / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": "classical fp64 oracle_gemm_f64 on the first %d of %d rows of C = A*B + C "
+    def bounded(Ad, Bd, seconds, align):
+        """Times the first rows of Ad @ Bd, rows sized for `seconds`."""
+        m = Ad.shape[0]
+        probe = min(m, max(align, 4))
+        t = classical(Ad, Bd, probe)
+        rows = int(min(m, max(probe, probe * seconds / max(t, 1e-6))))
+        rows = min(m, max(align, (rows // align) * align))
+        t = classical(Ad, Bd, rows)
+        return rows, t
+
+    n, k = B.shape[1], A.shape[1]
+    Bd = oracle._f64(B)
+    # headline: the first rows of the 16384^3 product
+    rows, t = bounded(oracle._f64(A), Bd, target_s, threads)
+    main = {"value": 2.0 * rows * n * k / t / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": "classical fp64 oracle_gemm_f64 on the first %d of %d rows of C = A*B "
                       "(n = k = %d), %.1f s" % (rows, A.shape[0], n, t)}
+    samples = []
+    rng = np.random.default_rng(7)
+
+    def shape_sample(name, m_, n_, k_, seconds=1.0):
+        Ad_ = rng.random((min(m_, 4096), k_)) * 2 - 1
+        Bd_ = Bd[:k_, :n_] if (k_ <= Bd.shape[0] and n_ <= Bd.shape[1]) else rng.random((k_, n_)) * 2 - 1
+        Bd_ = np.ascontiguousarray(Bd_)
+        r, tt = bounded(Ad_, Bd_, seconds, threads)
+        samples.append({"workload": name, "m": m_, "n": n_, "k": k_, "rows_timed": r, "seconds": round(tt, 3),
+                        "tflops": round(2.0 * r * n_ * k_ / tt / 1e12, 4), "kind": "classical fp64"})
+
+    shape_sample("small square", 1024, 1024, 1024)
+    for N in (2048, 4096, 8192, 12288):
+        shape_sample("square sweep", N, N, N)
+    for kk in (512, 1024, 2048, 4096):
+        shape_sample("rank-k sweep", 16384, 16384, kk, 0.5)
+    shape_sample("awkward", 15001, 17003, 9007)
+    shape_sample("awkward", 3000, 20000, 5000)
+    # the fp64 Strassen recursion (explicit zero-padded quadrant copies) on
+    # the small square
+    for N in (1024,):
+        A2 = rng.random((N, N)) * 2 - 1
+        B2 = rng.random((N, N)) * 2 - 1
+        for L in (0, 1, 2):
+            C2 = np.zeros((N, N))
+            t0 = time.perf_counter()
+            rc = lib.oracle_strassen(N, N, N, oracle._ptr(A2), N, oracle._ptr(B2), N, oracle._ptr(C2), N,
+                                     1.0, 0.0, L, 0)
+            tt = time.perf_counter() - t0
+            if rc:
+                raise SystemExit("oracle_strassen failed (%d)" % rc)
+            samples.append({"workload": "square, oracle_strassen fp64", "m": N, "n": N, "k": N,
+                            "levels": L, "seconds": round(tt, 3),
+                            "tflops": round(2.0 * N ** 3 / tt / 1e12, 4), "kind": "strassen fp64"})
+    # one core
+    try:
+        prev = _omp_set_threads(1)
+    except OSError:
+        prev = None
+    if prev is not None:
+        A2 = rng.random((2048, 2048)) * 2 - 1
+        B2 = rng.random((2048, 2048)) * 2 - 1
+        r, tt = bounded(A2, B2, 2.0, 1)
+        _omp_set_threads(prev)
+        samples.append({"workload": "square, one core", "m": 2048, "n": 2048, "k": 2048, "rows_timed": r,
+                        "seconds": round(tt, 3), "tflops": round(2.0 * r * 2048 * 2048 / tt / 1e12, 5),
+                        "kind": "classical fp64", "threads": 1})
+    main["host"] = host_cpu()
+    main["samples"] = samples
+    return main
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "strassen_f32_16384_traffic.md")
@@ -208,35 +311,125 @@ def precision_section(sizes, steps, dev, stream, log):
                 scale = N * float(Ah.float().abs().max()) * float(Bh.float().abs().max())
                 A, B = Ah.to(dev), Bh.to(dev)
                 C = torch.zeros(N, N, device=dev)
-                for L in (0, 1, 2):
-                    sg.gemm(A, B, C, 1.0, 0.0, levels=L, mode=mode)
+                ws = torch.empty(sg.api.formed_workspace_bytes(N, N, N, tdt, mode), dtype=torch.uint8,
+                                 device=dev)
+                for L in (0, 1, "1_formed", 2):
+                    if L == "1_formed":
+                        call = (lambda: sg.gemm_formed(A, B, C, 1.0, 0.0, mode=mode, workspace=ws))
+                        lv = 1
+                    else:
+                        call = (lambda L=L: sg.gemm(A, B, C, 1.0, 0.0, levels=L, mode=mode))
+                        lv = L
+                    call()
                     torch.cuda.synchronize()
                     err = np.abs(sampled_got(C, rows, cols) - want)
                     row = {"e_norm_gate": round(float(err.max()) / (eps_gate * scale), 5),
                            "rel_frobenius": float(np.sqrt((err ** 2).sum() / (want ** 2).sum())),
                            "componentwise_gate": round(float((err / (eps_gate * mag)).max()), 4),
-                           "gate_eps": eps_gate, "tolerance": 2.0 ** (L + 1)}
+                           "gate_eps": eps_gate, "tolerance": 2.0 ** (lv + 1)}
+                    if mode == "bf16x3":
+                        # the same error in units of fp32's eps (reported, not gated)
+                        row["e_norm_2m23"] = round(float(err.max()) / (2.0 ** -23 * scale), 4)
+                        row["componentwise_2m23"] = round(float((err / (2.0 ** -23 * mag)).max()), 3)
                     if dist == "normal":
-                        ms = time_calls(lambda: sg.gemm(A, B, C, 1.0, 0.0, levels=L, mode=mode),
-                                        steps, 1, stream)
-                        info = sg.plan_info(N, N, N, L, tdt, mode)
+                        ms = time_calls(call, steps, 1, stream)
+                        info = sg.plan_info(N, N, N, lv, tdt, mode)
                         mult = 3.0 if mode == "bf16x3" else 1.0
                         exe = mult * info.executed_flops / (ms * 1e-3) / 1e12
                         row.update({"ms_per_step": round(ms, 4),
                                     "effective_tflops": round(2.0 * N ** 3 / (ms * 1e-3) / 1e12, 2),
                                     "executed_mfma_tflops": round(exe, 2),
                                     "mfma_frac_executed": round(exe / BF16_MFMA_PEAK, 4)})
-                        log("%s N=%d L%d: %.3f ms  effective %.1f TFLOP/s  e_norm %.4f  rel_F %.2e"
+                        log("%s N=%d L%s: %.3f ms  effective %.1f TFLOP/s  e_norm %.4f%s  rel_F %.2e"
                             % (name, N, L, ms, row["effective_tflops"], row["e_norm_gate"],
+                               (" (%.3f at 2^-23)" % row["e_norm_2m23"]) if "e_norm_2m23" in row else "",
                                row["rel_frobenius"]))
                     else:
-                        log("%s N=%d L%d scaled: e_norm %.4f  rel_F %.2e  componentwise %.3f"
+                        log("%s N=%d L%s scaled: e_norm %.4f  rel_F %.2e  componentwise %.3f"
                             % (name, N, L, row["e_norm_gate"], row["rel_frobenius"],
                                row["componentwise_gate"]))
-                    res.setdefault(str(N), {}).setdefault(dist, {})["L%d" % L] = row
-                del A, B, C
+                    res.setdefault(str(N), {}).setdefault(dist, {})["L%s" % L] = row
+                del A, B, C, ws
                 torch.cuda.empty_cache()
         out[name] = res
+    return out
+
+
+def compensated_section(sizes, steps, rounds, dev, stream, log):
+    """The compensated bf16x3 mode on fp32 N(0,1) operands, C := A*B (the
+    precision workload) at m=n=k in `sizes`: the plain product, the fused
+    one-level call, the formed one-level call (two-term sums formed into
+    workspace first, bit-identical to the fused one) and the fused two-level
+    call, timed in `rounds` interleaved rounds of `steps` calls each (the
+    16-bit matrix cores run power-limited, so the variants are timed in
+    turn under the same conditions); the median round of each is reported.
+    Also: the formed call's form and product launch times (library events),
+    its equality with the fused call, and sampled errors at 2^-16 (the gate)
+    and 2^-23 (fp32's eps)."""
+    import numpy as np
+    import torch
+    import paper_1808_07984_amd as sg
+    from paper_1808_07984_amd import inputs
+
+    out = {}
+    for N in sizes:
+        A = inputs.normal(N, N, inputs.SEED_A).to(dev)
+        B = inputs.normal(N, N, inputs.SEED_B).to(dev)
+        C = torch.zeros(N, N, device=dev)
+        ws = torch.empty(sg.api.formed_workspace_bytes(N, N, N, torch.float32, "bf16x3"),
+                         dtype=torch.uint8, device=dev)
+        variants = {
+            "L0": lambda: sg.gemm(A, B, C, 1.0, 0.0, levels=0, mode="bf16x3"),
+            "L1_fused": lambda: sg.gemm(A, B, C, 1.0, 0.0, levels=1, mode="bf16x3"),
+            "L1_formed": lambda: sg.gemm_formed(A, B, C, 1.0, 0.0, mode="bf16x3", workspace=ws),
+            "L2_fused": lambda: sg.gemm(A, B, C, 1.0, 0.0, levels=2, mode="bf16x3"),
+        }
+        # correctness first: formed == fused, sampled errors vs fp64
+        rng = np.random.default_rng(N + 1)
+        rows, cols = rng.integers(0, N, 256), rng.integers(0, N, 256)
+        want, _ = sampled_reference(A, B, None, rows, cols, 1.0, 0.0)
+        scale = N * float(A.abs().max()) * float(B.abs().max())
+        errs = {}
+        ref1 = None
+        for name, fn in variants.items():
+            fn()
+            torch.cuda.synchronize()
+            err = float(np.abs(sampled_got(C, rows, cols) - want).max())
+            errs[name] = {"e_norm_2m16": round(err / (2.0 ** -16 * scale), 5),
+                          "e_norm_2m23": round(err / (2.0 ** -23 * scale), 4)}
+            if name == "L1_fused":
+                ref1 = C.clone()
+            if name == "L1_formed" and not torch.equal(C, ref1):
+                raise SystemExit("formed one-level result differs from the fused one at N=%d" % N)
+        del ref1
+        times = {name: [] for name in variants}
+        for _ in range(rounds):
+            for name, fn in variants.items():
+                times[name].append(time_calls(fn, steps, 1, stream))
+        # the formed call's launches
+        sg.strassen_profile_start()
+        variants["L1_formed"]()
+        rc, recs = sg.strassen_profile_stop()
+        forms = sum(r.ms for r in recs if r.kernel.decode().startswith("form_sums"))
+        prods = sum(r.ms for r in recs if not r.kernel.decode().startswith("form_sums"))
+        row = {}
+        for name, ts in times.items():
+            ms = float(np.median(ts))
+            row[name] = {"ms_per_step": round(ms, 4), "rounds_ms": [round(t, 4) for t in ts],
+                         "effective_tflops": round(2.0 * N ** 3 / (ms * 1e-3) / 1e12, 2), **errs[name]}
+        row["L1_formed"]["form_ms"] = round(forms, 4)
+        row["L1_formed"]["product_ms"] = round(prods, 4)
+        row["L1_formed"]["workspace_bytes"] = int(ws.numel())
+        row["L1_formed_vs_L0"] = round(row["L0"]["ms_per_step"] / row["L1_formed"]["ms_per_step"], 4)
+        row["L1_fused_vs_L0"] = round(row["L0"]["ms_per_step"] / row["L1_fused"]["ms_per_step"], 4)
+        out[str(N)] = row
+        log("bf16x3 N=%d (median of %d rounds): L0 %.3f  L1 fused %.3f  L1 formed %.3f (forms %.3f)  "
+            "L2 %.3f ms;  formed speedup over plain %.3fx, fused %.3fx"
+            % (N, rounds, row["L0"]["ms_per_step"], row["L1_fused"]["ms_per_step"],
+               row["L1_formed"]["ms_per_step"], forms, row["L2_fused"]["ms_per_step"],
+               row["L1_formed_vs_L0"], row["L1_fused_vs_L0"]))
+        del A, B, C, ws
+        torch.cuda.empty_cache()
     return out
 
 
@@ -495,9 +688,15 @@ def main():
                 "flops_per_launch": dom_flops / dom_n}
 
     sweep = awkward = None
-    if args.sweep:
+    if not args.no_sweep:
         sweep = sweep_section(A, B, C0, max(1, min(args.steps, 3)), dev, stream, log)
         awkward = awkward_section(A, B, C0, max(1, min(args.steps, 3)), dev, stream, log)
+
+    compensated = None
+    if not args.no_compensated:
+        log("compensated section: bf16x3 plain / fused / formed at m=n=k in (8192, %d)" % N)
+        compensated = compensated_section(tuple(s_ for s_ in (8192, N) if s_ <= N),
+                                          max(2, min(args.steps, 5)), 3, dev, stream, log)
 
     precision = None
     if not args.no_precision:
@@ -549,6 +748,12 @@ def main():
     if awkward is not None:
         result["awkward"] = {"workload": "fp32 C = 1.5*A*B + 0.5*C, NaN in the leading-dimension "
                                          "padding, A,B,C ~ U[-1,1] seeded", **awkward}
+    if compensated is not None:
+        result["compensated"] = {"workload": "bf16x3 mode, fp32 A,B ~ N(0,1) seeded, C := A*B, "
+                                             "m=n=k=N; plain (L0), fused one-level, formed one-level "
+                                             "(sums in workspace), fused two-level; median of "
+                                             "interleaved rounds; errors on 256 sampled entries vs "
+                                             "fp64 in units of N*max|A|*max|B|*eps", **compensated}
     if precision is not None:
         result["precision"] = {"workload": "C := A*B (beta 0), m=n=k in {4096, 8192, %d}; A,B ~ N(0,1) "
                                            "seeded (timed) and rows of A / columns of B scaled to "

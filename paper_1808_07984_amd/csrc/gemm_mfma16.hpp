@@ -896,6 +896,48 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
 #pragma unroll
     for (int o = 0; o < WC; ++o)
         c_full = c_full && row0 + C::MT <= crows[o] && col0 + C::NT <= ccols[o];
+    // With up to two outputs on 256-wide tiles the reads of the next 32x32
+    // block are issued before the stores of the current one (the staging
+    // registers are free after the k loop), so one block's read latency
+    // overlaps the previous block's stores: -1 % (4096^2 blocks) to -2 %
+    // (8192^2) for the single-term compensated products with two outputs,
+    // bit-identical.  With four outputs the second register set spills.
+    if (c_full && WC <= 2 && C::MT == 256) {
+        constexpr int NB = C::BM * C::BN;
+        float cv[2][WC][16];
+        auto cptr = [&](int b, int o) __attribute__((always_inline)) {
+            const int cj = col0 + wn * C::WN + (b % C::BN) * 32 + l32;
+            const int ci0 = row0 + wm * C::WM + (b / C::BN) * 32 + 4 * h;
+            return Cm + coff[o] + (int64_t)ci0 * ldc + cj;
+        };
+        auto cload = [&](int b) __attribute__((always_inline)) {
+#pragma unroll
+            for (int o = 0; o < WC; ++o) {
+                if (cfirst[o] && beta == 0.f) continue;
+                const float *pc = cptr(b, o);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) cv[b & 1][o][r] = pc[(int64_t)(8 * (r >> 2) + (r & 3)) * ldc];
+            }
+        };
+        cload(0);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if (b + 1 < NB) cload(b + 1);
+            const int i = b / C::BN, j = b % C::BN;
+#pragma unroll
+            for (int o = 0; o < WC; ++o) {
+                float *pc = cptr(b, o);
+                const bool read = !(cfirst[o] && beta == 0.f);
+                const float cb = cfirst[o] ? beta : 1.f;
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    pc[(int64_t)(8 * (r >> 2) + (r & 3)) * ldc] =
+                        read ? cb * cv[b & 1][o][r] + g[o] * acc[i][j][r] : g[o] * acc[i][j][r];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        return;
+    }
     if (c_full) {
 #pragma unroll
         for (int i = 0; i < C::BM; ++i)

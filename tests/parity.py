@@ -71,3 +71,36 @@ def to_device(prob, device="cuda"):
         out[name] = view
         out[name + "_storage"] = st
     return out
+
+
+def stratified_entries(m, n, levels, seed, tile=256, lanes_tiles=3):
+    """(rows, cols) covering every tile x tile square of every C block of the
+    library's levels-level partition with one random entry each, the four
+    corners of every block, and complete 32 x 32 accumulator blocks (every
+    lane and register of the MFMA output layout) at the first, a middle and
+    the last tile of the grid: a wrong tile, a wrong block or a wrong lane
+    position cannot escape."""
+    import paper_1808_07984_amd as sg
+    info = sg.plan_info(m, n, 1, levels)
+    sm, sn, d = info.sub_m, info.sub_n, info.blocks_per_dim
+    rng = np.random.default_rng(seed)
+    rows, cols = [], []
+    tiles = []
+    for R in range(d):
+        r0, r1 = R * sm, min((R + 1) * sm, m)
+        for Cc in range(d):
+            c0, c1 = Cc * sn, min((Cc + 1) * sn, n)
+            if r0 >= r1 or c0 >= c1:
+                continue
+            for tr in range(r0, r1, tile):
+                for tc in range(c0, c1, tile):
+                    tiles.append((tr, tc))
+                    rows.append(rng.integers(tr, min(tr + tile, r1)))
+                    cols.append(rng.integers(tc, min(tc + tile, c1)))
+            rows += [r0, r0, r1 - 1, r1 - 1]
+            cols += [c0, c1 - 1, c0, c1 - 1]
+    for (tr, tc) in (tiles[0], tiles[len(tiles) // 2], tiles[-1])[:lanes_tiles]:
+        rr, cc = np.meshgrid(np.arange(tr, min(tr + 32, m)), np.arange(tc, min(tc + 32, n)), indexing="ij")
+        rows += rr.ravel().tolist()
+        cols += cc.ravel().tolist()
+    return np.asarray(rows, dtype=np.int64), np.asarray(cols, dtype=np.int64)

@@ -8,7 +8,7 @@ import torch
 
 import oracle
 import paper_1808_07984_amd as sg
-from parity import EPS, e_norm, make_problem, tau, to_device
+from parity import EPS, e_norm, make_problem, stratified_entries, tau, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -97,9 +97,7 @@ def _sampled(m, n, k, alpha, beta, lda=None, ldb=None, ldc=None, kind="uniform",
     prob = make_problem(m, n, k, kind=kind, c_kind=kind, lda=lda, ldb=ldb, ldc=ldc,
                         int_range=(-1, 1))
     dev = _run(prob, alpha, beta)
-    rng = np.random.default_rng(m + n + k)
-    rows = np.concatenate([rng.integers(0, m, 400), [0, m - 1]])
-    cols = np.concatenate([rng.integers(0, n, 400), [n - 1, 0]])
+    rows, cols = stratified_entries(m, n, 2, m + n + k)
     want = oracle.gemm_entries(prob["A"], prob["B"], prob["C"], rows, cols, alpha, beta)
     got = dev["C"][torch.as_tensor(rows, device="cuda"),
                    torch.as_tensor(cols, device="cuda")].double().cpu().numpy()

@@ -15,7 +15,7 @@ import torch
 
 import oracle
 import paper_1808_07984_amd as sg
-from parity import EPS, e_norm, make_problem, tau, to_device
+from parity import EPS, e_norm, make_problem, stratified_entries, tau, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -131,15 +131,16 @@ def test_lowp_deterministic():
 
 @pytest.mark.parametrize("kind,levels", [("bf16", 2), ("f16", 1), ("bf16x3", 2)])
 def test_lowp_full_size_sampled(kind, levels):
-    """m = n = k = 16384 (the precision configuration's largest size), sampled
-    entries against the classical fp64 definition on the stored operands."""
+    """m = n = k = 16384 (the precision configuration's largest size),
+    stratified entries (every tile of every C block, block corners, whole
+    32 x 32 accumulator blocks) against the classical fp64 definition on the
+    stored operands."""
     dtype, mode = MODES[kind]
     N = 16384
     dist = "uniform" if kind == "bf16x3" else "normal"
     prob = make_problem(N, N, N, kind=dist, dtype=dtype, c_kind="zeros")
     dev = _run(prob, levels, 1.0, 0.0, mode)
-    rng = np.random.default_rng(levels)
-    rows, cols = rng.integers(0, N, 400), rng.integers(0, N, 400)
+    rows, cols = stratified_entries(N, N, levels, levels)
     want = oracle.gemm_entries(prob["A"], prob["B"], None, rows, cols, 1.0, 0.0)
     got = dev["C"][torch.as_tensor(rows, device="cuda"),
                    torch.as_tensor(cols, device="cuda")].double().cpu().numpy()

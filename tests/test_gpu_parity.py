@@ -18,7 +18,7 @@ import torch
 import oracle
 import paper_1808_07984_amd as sg
 from paper_1808_07984_amd import inputs
-from parity import EPS, e_norm, make_problem, tau, to_device
+from parity import EPS, e_norm, make_problem, stratified_entries, tau, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -167,28 +167,39 @@ def test_no_device_allocation():
     assert free1 == free0
 
 
-def _sampled(m, n, k, levels, alpha, beta, lda=None, ldb=None, ldc=None, kind="uniform",
-             nsamp=512, exact=False):
-    """Full-size call, compared on sampled entries against oracle.gemm_entries."""
-    prob = make_problem(m, n, k, kind=kind, c_kind=kind, lda=lda, ldb=ldb, ldc=ldc,
-                        int_range=(-1, 1))
-    dev = _run(prob, levels, alpha, beta)
-    rng = np.random.default_rng(m + n + k + levels)
-    rows = np.concatenate([rng.integers(0, m, nsamp), [0, m - 1, m - 1, 0]])
-    cols = np.concatenate([rng.integers(0, n, nsamp), [0, n - 1, 0, n - 1]])
+def _check_entries(prob, Cg, rows, cols, k, levels, alpha, beta, exact):
     want = oracle.gemm_entries(prob["A"], prob["B"], prob["C"], rows, cols, alpha, beta)
-    Cg = dev["C"]
     got = Cg[torch.as_tensor(rows, device="cuda"), torch.as_tensor(cols, device="cuda")].cpu().double().numpy()
     if exact:
-        assert np.array_equal(got, want)
+        bad = int((got != want).sum())
+        print("stratified: %d entries, %d differ (exact)" % (len(rows), bad), flush=True)
+        assert bad == 0
+        return
+    amax = float(prob["A"].abs().max())
+    bmax = float(prob["B"].abs().max())
+    cmax = float(prob["C"].abs().max())
+    scale = k * abs(alpha) * amax * bmax + abs(beta) * cmax
+    en = float(np.abs(got - want).max()) / (EPS["f32"] * scale)
+    print("stratified: %d entries, e_norm=%.4f (tau=%g)" % (len(rows), en, tau(levels)), flush=True)
+    assert en <= tau(levels)
+
+
+def _sampled(m, n, k, levels, alpha, beta, lda=None, ldb=None, ldc=None, kind="uniform",
+             exact=False, call=None):
+    """Full-size call, compared against oracle.gemm_entries on the
+    stratified entries (every tile of every C block, block corners, whole
+    32 x 32 accumulator blocks)."""
+    prob = make_problem(m, n, k, kind=kind, c_kind=kind, lda=lda, ldb=ldb, ldc=ldc,
+                        int_range=(-1, 1))
+    if call is None:
+        dev = _run(prob, levels, alpha, beta)
     else:
-        amax = float(prob["A"].abs().max())
-        bmax = float(prob["B"].abs().max())
-        cmax = float(prob["C"].abs().max())
-        scale = k * abs(alpha) * amax * bmax + abs(beta) * cmax
-        en = float(np.abs(got - want).max()) / (EPS["f32"] * scale)
-        print("sampled e_norm=%.4f (tau=%g)" % (en, tau(levels)), flush=True)
-        assert en <= tau(levels)
+        dev = to_device(prob)
+        call(dev, alpha, beta)
+        torch.cuda.synchronize()
+    rows, cols = stratified_entries(m, n, levels, m + n + k + levels)
+    Cg = dev["C"]
+    _check_entries(prob, Cg, rows, cols, k, levels, alpha, beta, exact)
     assert bool(torch.isfinite(Cg).all())
     if ldc and ldc > n:
         assert bool(torch.isnan(dev["C_storage"][:, n:]).all())
@@ -199,7 +210,28 @@ def test_full_size_square_16384(levels):
     _sampled(16384, 16384, 16384, levels, 1.0, 1.0)
 
 
-@pytest.mark.parametrize("k", [512, 4096])
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_full_size_square_16384_integer_exact(levels):
+    """Entries in {-1, 0, 1}: the largest intermediate (about 1.0e6 at two
+    levels) is below 2^24, so every checked entry is exact."""
+    _sampled(16384, 16384, 16384, levels, 1.0, 1.0, kind="integers", exact=True)
+
+
+def test_full_size_hybrid_16384():
+    def call(dev, alpha, beta):
+        print("case hybrid 16384^3", flush=True)
+        sg.gemm_hybrid(dev["A"], dev["B"], dev["C"], alpha, beta)
+    _sampled(16384, 16384, 16384, 2, 1.0, 1.0, call=call)
+
+
+def test_full_size_hybrid_16384_integer_exact():
+    def call(dev, alpha, beta):
+        print("case hybrid 16384^3 integers", flush=True)
+        sg.gemm_hybrid(dev["A"], dev["B"], dev["C"], alpha, beta)
+    _sampled(16384, 16384, 16384, 2, 1.0, 1.0, kind="integers", exact=True, call=call)
+
+
+@pytest.mark.parametrize("k", [512, 1024, 2048, 4096])
 @pytest.mark.parametrize("levels", [0, 1, 2])
 def test_full_size_rank_k(k, levels):
     """Rank-k updates m = n = 16384 (k = 512 at two levels: 128-deep blocks,
@@ -212,21 +244,47 @@ def test_full_size_square_12288(levels):
     _sampled(12288, 12288, 12288, levels, 1.0, 1.0)
 
 
-@pytest.mark.parametrize("levels", [2])
+@pytest.mark.parametrize("levels", [0, 1, 2])
 def test_full_size_awkward_15001(levels):
     _sampled(15001, 17003, 9007, levels, 1.5, 0.5, lda=9024, ldb=17024, ldc=17024)
 
 
-@pytest.mark.parametrize("levels", [2])
+@pytest.mark.parametrize("levels", [0, 1, 2])
 def test_full_size_awkward_3000(levels):
     _sampled(3000, 20000, 5000, levels, 1.5, 0.5, lda=5056, ldb=20032, ldc=20032)
 
 
-def test_full_size_awkward_integer_exact():
-    """Entries in {-1, 0, 1}: exact at every sampled entry (largest
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_full_size_awkward_integer_exact(levels):
+    """Entries in {-1, 0, 1}: exact at every checked entry (largest
     intermediate well below 2^23)."""
-    _sampled(15001, 17003, 9007, 2, 1.5, 0.5, lda=9024, ldb=17024, ldc=17024,
+    _sampled(15001, 17003, 9007, levels, 1.5, 0.5, lda=9024, ldb=17024, ldc=17024,
              kind="integers", exact=True)
+
+
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_base_entry_point_on_a_set_stream(levels):
+    """strassen_gemm (the fp32 entry point without dtype, mode or stream
+    arguments) on a stream chosen with strassen_set_stream: exact on
+    integers, and the work is ordered on that stream."""
+    m, n, k = 1100, 1060, 600
+    prob = make_problem(m, n, k, kind="integers", c_kind="integers")
+    dev = to_device(prob)
+    A, B, C = dev["A"], dev["B"], dev["C"]
+    s = torch.cuda.Stream()
+    assert sg.strassen_set_stream(s.cuda_stream) == 0
+    try:
+        print("case strassen_gemm on a set stream L=%d" % levels, flush=True)
+        rc = sg.strassen_gemm(m, n, k, A.data_ptr(), A.stride(0), B.data_ptr(), B.stride(0),
+                              C.data_ptr(), C.stride(0), 1.0, 1.0, levels)
+        assert rc == 0
+        done = torch.cuda.Event()
+        done.record(s)
+        done.synchronize()
+    finally:
+        sg.strassen_set_stream(None)
+    want = oracle.gemm_f64(prob["A"], prob["B"], prob["C"], 1.0, 1.0)
+    assert np.array_equal(C.cpu().double().numpy(), want)
 
 
 def _wide(x, ld):
