@@ -33,7 +33,7 @@
  *   -i              the i-th argument of the called function is invalid
  *                   (1-based, in that function's parameter order)
  *   > 0             a hipError_t reported by the HIP runtime (no device,
- *                   launch failure, ...)
+ *                   launch failure, ...), or STRASSEN_ERROR_SCRATCH_LIMIT
  * strassen_error_string() describes a code.  No C++ exception crosses the ABI.
  *
  * Degenerate cases (BLAS conventions; the paper fixes alpha = beta = 1):
@@ -167,6 +167,31 @@ int strassen_gemm_formed(int64_t m, int64_t n, int64_t k,
  * argument index (m=1 n=2 k=3 dtype=4 mode=5).  Pure host computation. */
 int64_t strassen_formed_workspace_size(int64_t m, int64_t n, int64_t k,
                                        strassen_dtype_t dtype, strassen_mode_t mode);
+
+/* strassen_gemm_formed without a workspace argument and without any
+ * allocation, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * operand sums go to a fixed scratch array of STRASSEN_NOALLOC_SCRATCH_BYTES
+ * (256 MiB) that the library's code object holds on every GPU it runs on,
+ * from module load until the process ends.  Same arguments, semantics and
+ * results as strassen_gemm_formed (minus the workspace pair; argument
+ * indices as there, hip_stream=15).  A call whose
+ * strassen_formed_workspace_size exceeds the scratch returns
+ * STRASSEN_ERROR_SCRATCH_LIMIT without launching anything (fp32 data up to
+ * about m = n = k = 5180, 16-bit data up to about 7320).  All calls on one
+ * GPU share that GPU's scratch: calls that overlap in time on one GPU (from
+ * several streams or threads) race.  Nothing needs clearing between calls:
+ * every scratch element a call reads was written earlier in that call.  The
+ * scratch belongs to the device of hip_stream (the current device for the
+ * null stream); its address is looked up on the first call per device. */
+#define STRASSEN_NOALLOC_SCRATCH_BYTES ((int64_t)256 << 20)
+#define STRASSEN_ERROR_SCRATCH_LIMIT 0x5c00
+int strassen_gemm_formed_noalloc(int64_t m, int64_t n, int64_t k,
+                                 const void *A, int64_t lda, strassen_dtype_t a_type,
+                                 const void *B, int64_t ldb, strassen_dtype_t b_type,
+                                 float *C, int64_t ldc,
+                                 float alpha, float beta, strassen_mode_t mode,
+                                 void *hip_stream);
 
 /* Sets the stream strassen_gemm uses on the calling thread (a hipStream_t;
  * NULL = the null stream).  Always returns 0. */

@@ -34,6 +34,9 @@ from ._binding import (  # noqa: F401
     strassen_gemm,
     strassen_gemm_ex,
     strassen_gemm_formed,
+    strassen_gemm_formed_noalloc,
+    STRASSEN_NOALLOC_SCRATCH_BYTES,
+    STRASSEN_ERROR_SCRATCH_LIMIT,
     strassen_formed_workspace_size,
     strassen_gemm_hybrid,
     strassen_hybrid_workspace_size,

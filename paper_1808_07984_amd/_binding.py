@@ -74,6 +74,8 @@ SIGNATURES = {
     "strassen_gemm_formed": (_int, [_i64, _i64, _i64, _vp, _i64, _int, _vp, _i64, _int, _vp, _i64,
                                     _f32, _f32, _int, _vp, _i64, _vp]),
     "strassen_formed_workspace_size": (_i64, [_i64, _i64, _i64, _int, _int]),
+    "strassen_gemm_formed_noalloc": (_int, [_i64, _i64, _i64, _vp, _i64, _int, _vp, _i64, _int, _vp,
+                                            _i64, _f32, _f32, _int, _vp]),
     "strassen_set_stream": (_int, [_vp]),
     "strassen_set_tile": (_int, [_int]),
     "strassen_set_schedule": (_int, [_int]),
@@ -159,6 +161,16 @@ def strassen_gemm_formed(m, n, k, A, lda, a_type, B, ldb, b_type, C, ldc, alpha,
                          workspace, workspace_bytes, hip_stream):
     return lib.strassen_gemm_formed(m, n, k, A, lda, a_type, B, ldb, b_type, C, ldc, alpha, beta,
                                     mode, workspace, workspace_bytes, hip_stream)
+
+
+STRASSEN_NOALLOC_SCRATCH_BYTES = 256 << 20
+STRASSEN_ERROR_SCRATCH_LIMIT = 0x5C00
+
+
+def strassen_gemm_formed_noalloc(m, n, k, A, lda, a_type, B, ldb, b_type, C, ldc, alpha, beta, mode,
+                                 hip_stream):
+    return lib.strassen_gemm_formed_noalloc(m, n, k, A, lda, a_type, B, ldb, b_type, C, ldc, alpha,
+                                            beta, mode, hip_stream)
 
 
 def strassen_formed_workspace_size(m, n, k, dtype=STRASSEN_F32, mode=STRASSEN_MODE_PLAIN):

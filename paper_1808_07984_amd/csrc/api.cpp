@@ -958,6 +958,32 @@ int strassen_gemm_formed(int64_t m, int64_t n, int64_t k, const void *A, int64_t
     }
 }
 
+static_assert(strassen::kNoAllocScratchBytes == STRASSEN_NOALLOC_SCRATCH_BYTES,
+              "scratch size in the header and the library agree");
+
+int strassen_gemm_formed_noalloc(int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
+                                 strassen_dtype_t a_type, const void *B, int64_t ldb,
+                                 strassen_dtype_t b_type, float *C, int64_t ldc, float alpha,
+                                 float beta, strassen_mode_t mode, void *hip_stream) {
+    const Call c{m, n, k, A, lda, a_type, 0, B, ldb, b_type, 0, C, ldc,
+                 alpha, beta, 1, mode, (hipStream_t)hip_stream};
+    const int v = validate(c);
+    if (v != 0) return to_formed_index(v);
+    const bool product = m > 0 && n > 0 && k > 0 && alpha != 0.f;
+    try {
+        if (!product) return run_formed(c, nullptr);
+        const int64_t need = strassen_formed_workspace_size(m, n, k, a_type, mode);
+        if (need < 0) return (int)(-need);
+        if (need > strassen::kNoAllocScratchBytes) return STRASSEN_ERROR_SCRATCH_LIMIT;
+        void *scratch = nullptr;
+        const hipError_t err = strassen::noalloc_scratch(c.stream, &scratch);
+        if (err != hipSuccess) return (int)err;
+        return run_formed(c, scratch);
+    } catch (...) {
+        return (int)hipErrorOutOfMemory;
+    }
+}
+
 int strassen_set_stream(void *hip_stream) {
     g_stream = (hipStream_t)hip_stream;
     return 0;
@@ -1059,6 +1085,8 @@ int strassen_plan_instances(int levels, strassen_instance_t *out, int capacity) 
 
 const char *strassen_error_string(int code) {
     if (code == 0) return "success";
+    if (code == STRASSEN_ERROR_SCRATCH_LIMIT)
+        return "the call needs more workspace than the no-allocation entry point's fixed scratch holds";
     if (code < 0) {
         const int i = -code;
         if (i >= 1 && i <= (int)(sizeof(kArgMessages) / sizeof(kArgMessages[0])))

@@ -89,6 +89,13 @@ hipError_t launch_form_sums(FormElem elem, const FormSource *src, int nsrc, int6
                             const FormOut *out, int nout, int64_t ld_out, int64_t rows, int64_t cols,
                             bool vec, hipStream_t s);
 
+// strassen_gemm_formed_noalloc: the device address of the library's fixed
+// scratch array (kNoAllocScratchBytes, 256-byte aligned) on the device of
+// `stream` (the current device for the null stream), looked up once per
+// device.
+constexpr int64_t kNoAllocScratchBytes = (int64_t)256 << 20;
+hipError_t noalloc_scratch(hipStream_t stream, void **ptr);
+
 // C := beta * C over an m x n matrix (beta == 0 writes zeros, C not read).
 hipError_t launch_scale(float *C, int64_t ldc, int64_t m, int64_t n, float beta, hipStream_t s);
 
