@@ -274,6 +274,12 @@ int strassen_plan_instances(int levels, strassen_instance_t *out, int capacity);
 /* Static description of an error code; never NULL. */
 const char *strassen_error_string(int code);
 
+/* Identifier of the sources the library was built from (hex sha256 over its
+ * C++/HIP sources and this header, computed by the build script); the
+ * Python binding refuses a library whose id differs from the sources beside
+ * it.  Never NULL. */
+const char *strassen_build_id(void);
+
 /* ---- measurement support (Experiment section: kernels are timed with
  * device events) ----------------------------------------------------------
  * While recording is on, every kernel the library launches is bracketed by

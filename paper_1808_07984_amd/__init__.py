@@ -30,6 +30,7 @@ from ._binding import (  # noqa: F401
     STRASSEN_TILE_256,
     STRASSEN_TILE_AUTO,
     StrassenError,
+    strassen_build_id,
     strassen_error_string,
     strassen_gemm,
     strassen_gemm_ex,

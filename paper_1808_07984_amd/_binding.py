@@ -83,6 +83,7 @@ SIGNATURES = {
                                   ctypes.POINTER(strassen_plan_info_t)]),
     "strassen_plan_instances": (_int, [_int, ctypes.POINTER(strassen_instance_t), _int]),
     "strassen_error_string": (ctypes.c_char_p, [_int]),
+    "strassen_build_id": (ctypes.c_char_p, []),
     "strassen_profile_start": (_int, []),
     "strassen_profile_stop": (_int, [ctypes.POINTER(strassen_launch_record_t), _int]),
 }
@@ -123,7 +124,31 @@ def _load():
         fn.restype = res
         fn.argtypes = args
     check_single_hip_runtime()
+    built = lib.strassen_build_id().decode()
+    want = source_id()
+    if want is not None and built != want:
+        raise ImportError("libstrassen.so (%s) was built from other sources than those in %s (%s): "
+                          "rebuild with `python paper_1808_07984_amd/build.py`"
+                          % (built[:12], os.path.join(_HERE, "csrc"), want[:12]))
     return lib
+
+
+def source_id():
+    """The build id of the sources beside this file (same rule as
+    build.source_id), or None when they are not shipped."""
+    import hashlib
+    csrc = os.path.join(_HERE, "csrc")
+    include = os.path.join(os.path.dirname(_HERE), "include")
+    if not (os.path.isdir(csrc) and os.path.isdir(include)):
+        return None
+    h = hashlib.sha256()
+    for d in (csrc, include):
+        for name in sorted(os.listdir(d)):
+            if name.endswith((".hip", ".cpp", ".hpp", ".h")):
+                h.update(name.encode())
+                with open(os.path.join(d, name), "rb") as f:
+                    h.update(f.read())
+    return h.hexdigest()
 
 
 lib = _load()
@@ -214,6 +239,10 @@ def strassen_plan_instances(levels, capacity=None):
 def strassen_error_string(code):
     s = lib.strassen_error_string(code)
     return s.decode() if s else ""
+
+
+def strassen_build_id():
+    return lib.strassen_build_id().decode()
 
 
 def strassen_profile_start():

@@ -33,15 +33,32 @@ DEVICE = ["-x", "hip", "--offload-arch=" + ARCH,
           "-ffp-contract=fast", "-munsafe-fp-atomics"]
 
 
+def source_id():
+    """sha256 over the library's sources (csrc/ and include/, file names and
+    bytes, sorted): the build id compiled into the library, which the
+    binding compares with the sources next to it before loading it."""
+    import hashlib
+    h = hashlib.sha256()
+    for d in (CSRC, INCLUDE):
+        for name in sorted(os.listdir(d)):
+            if name.endswith((".hip", ".cpp", ".hpp", ".h")):
+                h.update(name.encode())
+                with open(os.path.join(d, name), "rb") as f:
+                    h.update(f.read())
+    return h.hexdigest()
+
+
 def _hipcc():
     rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
     return os.path.join(rocm, "bin", "hipcc")
 
 
-def _compile(src, verbose):
+def _compile(src, verbose, build_id):
     path = os.path.join(CSRC, src)
     obj = os.path.join(OUT_DIR, src + ".o")
     cmd = [_hipcc()] + COMMON
+    if src == "api.cpp":
+        cmd += ['-DSTRASSEN_BUILD_ID="%s"' % build_id]
     if src.endswith(".hip"):
         cmd += DEVICE
     cmd += ["-c", path, "-o", obj]
@@ -56,8 +73,9 @@ def _compile(src, verbose):
 def build(verbose=False, jobs=None):
     os.makedirs(OUT_DIR, exist_ok=True)
     jobs = jobs or min(len(SOURCES), os.cpu_count() or 4)
+    build_id = source_id()
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, verbose, build_id), SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [_hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH] + objs + ["-o", tmp]
     if verbose:

@@ -1083,6 +1083,12 @@ int strassen_plan_instances(int levels, strassen_instance_t *out, int capacity) 
     }
 }
 
+#ifndef STRASSEN_BUILD_ID
+#define STRASSEN_BUILD_ID "unknown"
+#endif
+
+const char *strassen_build_id(void) { return STRASSEN_BUILD_ID; }
+
 const char *strassen_error_string(int code) {
     if (code == 0) return "success";
     if (code == STRASSEN_ERROR_SCRATCH_LIMIT)

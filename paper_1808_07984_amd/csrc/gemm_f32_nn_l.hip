@@ -1,4 +1,6 @@
-// Instantiation of the fp32 Strassen kernels: A and B as stored, 256x256x16 tile.
+// Instantiation of the fp32 Strassen kernels: A and B as stored, 256x256 tile
+// (32-deep k-tiles; 16-deep for variants with more than four operand terms
+// other than (4,1,4) and (4,2,2)).
 #include "gemm_f32.hpp"
 
 namespace strassen {

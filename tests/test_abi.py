@@ -202,3 +202,10 @@ def test_formed_validation():
     assert call(C=A + 128) == -10         # A overlaps C
     assert call(m=0, A=None, B=None, C=None, ws=None) == 0
     assert call(n=0, A=None, B=None, C=None, ws=None) == 0
+
+
+def test_build_id_matches_sources():
+    """The loaded library was built from the sources in the tree (the binding
+    refuses to load one that was not)."""
+    assert sg.strassen_build_id() == _binding.source_id()
+    assert len(sg.strassen_build_id()) == 64
