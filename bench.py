@@ -364,8 +364,9 @@ def compensated_section(sizes, steps, rounds, dev, stream, log):
     16-bit matrix cores run power-limited, so the variants are timed in
     turn under the same conditions); the median round of each is reported.
     Also: the formed call's form and product launch times (library events),
-    its equality with the fused call, and sampled errors at 2^-16 (the gate)
-    and 2^-23 (fp32's eps)."""
+    its equality with the fused call on the blocks the chained products do
+    not touch, and sampled errors at 2^-16 (the gate) and 2^-23 (fp32's
+    eps)."""
     import numpy as np
     import torch
     import paper_1808_07984_amd as sg
@@ -399,8 +400,13 @@ def compensated_section(sizes, steps, rounds, dev, stream, log):
                           "e_norm_2m23": round(err / (2.0 ** -23 * scale), 4)}
             if name == "L1_fused":
                 ref1 = C.clone()
-            if name == "L1_formed" and not torch.equal(C, ref1):
-                raise SystemExit("formed one-level result differs from the fused one at N=%d" % N)
+            if name == "L1_formed":
+                # C1 and C2 equal the fused call bit for bit; C0 and C3 take the
+                # chained products (added together with their partners)
+                h = N // 2
+                if not (torch.equal(C[:h, h:], ref1[:h, h:]) and torch.equal(C[h:, :h], ref1[h:, :h])
+                        and errs[name]["e_norm_2m16"] <= 4.0):
+                    raise SystemExit("formed one-level result check failed at N=%d" % N)
         del ref1
         times = {name: [] for name in variants}
         for _ in range(rounds):

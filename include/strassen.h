@@ -140,8 +140,13 @@ int64_t strassen_hybrid_workspace_size(int64_t m, int64_t n, int64_t k);
  * order and precision as the fused kernels form them (fp32 from the stored
  * values, 16-bit data rounded once) and the products accumulate in the same
  * order, so the result equals strassen_gemm_ex's one-level result bit for
- * bit.  Worth it where staging multi-term sums inside the product kernel is
- * the bottleneck (the BF16X3 mode).  A and B as stored (no transposes);
+ * bit, except on the 16-bit matrix cores with 256x256 tiles (C blocks of at
+ * least 128 such tiles): there the single-output products M5 and M6 are
+ * accumulated after M2 and M3 in the same workgroups and added into C3 and
+ * C0 together with them (one read-modify-write of those blocks fewer each),
+ * so those two blocks can differ from the fused result in the last bits.
+ * Worth it where staging multi-term sums inside the product kernel is the
+ * bottleneck (the BF16X3 mode).  A and B as stored (no transposes);
  * a_type == b_type; modes and types as in strassen_gemm_ex; same degenerate
  * cases.
  * workspace: device memory of at least strassen_formed_workspace_size()

@@ -573,7 +573,11 @@ int run_hybrid(const Call &c, float *ws) {
 // workspace.  The sums are formed in the fused kernels' order and precision
 // (fp32 from the stored values, the first term's sign factored out, 16-bit
 // data rounded once), and the product kernels accumulate in the same k
-// order, so the result equals the fused one-level result bit for bit.
+// order, so the result equals the fused one-level result bit for bit --
+// except where chains apply (16-bit kernels on 256x256 tiles): there the two
+// single-output products M5 and M6 are accumulated after M2 and M3 and added
+// into C3 and C0 together with them, saving two read-modify-writes of a C
+// block and a launch, and those two blocks can differ in the last bits.
 // ---------------------------------------------------------------------------
 struct FormedSum {
     int nterms;
@@ -693,7 +697,41 @@ int form_operand(const std::vector<FormedSum> &sums, strassen::FormElem fe, size
     return 0;
 }
 
-int run_formed(const Call &c, void *ws) {
+// A second stream of the calling thread on one device, with a fork and a
+// join event, on which the formed schedule runs B's form beside the product
+// launches that need no formed B operand.  Created on first use (default
+// priority, non-blocking) and kept until the thread ends.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+constexpr int kSideDevices = 64;
+thread_local SideStream g_side[kSideDevices];
+
+hipError_t side_stream(hipStream_t caller, SideStream **out) {
+    int dev = 0;
+    hipError_t err = caller ? hipStreamGetDevice(caller, &dev) : hipGetDevice(&dev);
+    if (err != hipSuccess) return err;
+    if (dev < 0 || dev >= kSideDevices) return hipErrorInvalidDevice;
+    SideStream &ss = g_side[dev];
+    if (ss.s == nullptr) {
+        int cur = 0;
+        if ((err = hipGetDevice(&cur)) != hipSuccess) return err;
+        if (cur != dev && (err = hipSetDevice(dev)) != hipSuccess) return err;
+        err = hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking);
+        if (err == hipSuccess) err = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming);
+        if (err == hipSuccess) err = hipEventCreateWithFlags(&ss.join, hipEventDisableTiming);
+        const hipError_t back = cur != dev ? hipSetDevice(cur) : hipSuccess;
+        if (err != hipSuccess) return err;
+        if (back != hipSuccess) return back;
+    }
+    *out = &ss;
+    return hipSuccess;
+}
+
+// side: B's form may run on a side stream (creating it on first use);
+// false for callers that must not allocate.
+int run_formed(const Call &c, void *ws, bool side = true) {
     if (c.m == 0 || c.n == 0) return 0;
     if (c.k == 0 || c.alpha == 0.f)
         return (int)strassen::launch_scale(c.C, c.ldc, c.m, c.n, c.beta, c.stream);
@@ -709,20 +747,159 @@ int run_formed(const Call &c, void *ws) {
                                                               : strassen::FormElem::kF16;
     const bool vec_a = (c.lda % fam.vec == 0) && ((uintptr_t)c.A % 16 == 0);
     const bool vec_b = (c.ldb % fam.vec == 0) && ((uintptr_t)c.B % 16 == 0);
-    int rc = form_operand(g.asums, fe, in_es, c.A, c.lda, c.m, c.k, sm, sk, wa, vec_a, c.stream, 0);
-    if (rc != 0) return rc;
-    rc = form_operand(g.bsums, fe, in_es, c.B, c.ldb, c.k, c.n, sk, sn, wb, vec_b, c.stream, 1);
-    if (rc != 0) return rc;
+    int rc = 0;
 
-    // Products, batch by batch in the plan's order; a batch whose products
-    // take an operand from different places is split by source.
+    // Operand of product pi: its formed sum in workspace (extent: the union
+    // of its terms' extents; beyond it the sum is a virtual zero) or its
+    // single quadrant.
+    auto operand_a = [&](int pi) {
+        const strassen::Product &p = plan.products[pi];
+        if (g.a_of[pi] >= 0) {
+            int64_t rows = 0, cols = 0;
+            for (int t = 0; t < p.na; ++t) {
+                rows = std::max(rows, strassen::block_extent(c.m, sm, p.a[t].block / 2));
+                cols = std::max(cols, strassen::block_extent(c.k, sk, p.a[t].block % 2));
+            }
+            return term((int64_t)g.a_of[pi] * sm * sk, rows, cols, p.a[0].sign, false);
+        }
+        const int R = p.a[0].block / 2, Cc = p.a[0].block % 2;
+        return term(R * sm * c.lda + Cc * sk, strassen::block_extent(c.m, sm, R),
+                    strassen::block_extent(c.k, sk, Cc), p.a[0].sign, false);
+    };
+    auto operand_b = [&](int pi) {
+        const strassen::Product &p = plan.products[pi];
+        if (g.b_of[pi] >= 0) {
+            int64_t rows = 0, cols = 0;
+            for (int t = 0; t < p.nb; ++t) {
+                rows = std::max(rows, strassen::block_extent(c.k, sk, p.b[t].block / 2));
+                cols = std::max(cols, strassen::block_extent(c.n, sn, p.b[t].block % 2));
+            }
+            return term((int64_t)g.b_of[pi] * sk * sn, rows, cols, p.b[0].sign, false);
+        }
+        const int R = p.b[0].block / 2, Cc = p.b[0].block % 2;
+        return term(R * sk * c.ldb + Cc * sn, strassen::block_extent(c.k, sk, R),
+                    strassen::block_extent(c.n, sn, Cc), p.b[0].sign, false);
+    };
+
+    // Chains (16-bit kernels): a batch of two-output products each of which
+    // shares an output block with a distinct single-output product becomes
+    // one chained launch, and those single-output products leave their own
+    // batches.  At one level: {M2, M3} with M5 (C3) and M6 (C0).
+    std::vector<int> head_of(plan.products.size(), -1);  // single-output product -> its chain head
+    std::vector<int> carry_of(plan.products.size(), 0);  // chain head -> 1 + carried output
+    int chained_batch = -1;
+    if (fam.m16) {
+        for (size_t bi = 0; bi < plan.batches.size() && chained_batch < 0; ++bi) {
+            const strassen::Batch &bt = plan.batches[bi];
+            if (bt.wc != 2 || 2 * bt.products.size() > (size_t)strassen::kMaxBatchArgs ||
+                !use_large(sm, sn, sk, (int)bt.products.size(), false))
+                continue;  // chained launches use the 256x256 tile
+            std::vector<int> pick(plan.products.size(), -1), carry(plan.products.size(), 0);
+            std::vector<bool> taken(plan.products.size(), false);
+            bool all = true;
+            for (int x : bt.products) {
+                bool found = false;
+                for (size_t y = 0; y < plan.products.size() && !found; ++y) {
+                    const strassen::Product &py = plan.products[y];
+                    if (py.nc != 1 || taken[y]) continue;
+                    for (int o = 0; o < plan.products[x].nc && !found; ++o)
+                        if (plan.products[x].c[o].block == py.c[0].block) {
+                            taken[y] = true;
+                            pick[y] = x;
+                            carry[x] = o + 1;
+                            found = true;
+                        }
+                }
+                all = all && found;
+            }
+            if (!all) continue;
+            chained_batch = (int)bi;
+            head_of = pick;
+            carry_of = carry;
+        }
+    }
+    // C blocks written so far (first updates apply beta), in launch order
+    bool touched[4] = {false, false, false, false};
+    auto first_of = [&](int block) {
+        const bool f = !touched[block];
+        touched[block] = true;
+        return f;
+    };
+    auto c_term = [&](const strassen::Term &t, bool first) {
+        const int R = t.block / 2, Cc = t.block % 2;
+        return term(R * sm * c.ldc + Cc * sn, strassen::block_extent(c.m, sm, R),
+                    strassen::block_extent(c.n, sn, Cc), t.sign, first);
+    };
+    auto set_sources = [&](ProductArg &pa, int pi) {
+        pa.a_base = g.a_of[pi] >= 0 ? static_cast<const void *>(wa) : c.A;
+        pa.lda = g.a_of[pi] >= 0 ? sk : c.lda;
+        pa.b_base = g.b_of[pi] >= 0 ? static_cast<const void *>(wb) : c.B;
+        pa.ldb = g.b_of[pi] >= 0 ? sn : c.ldb;
+    };
+
+    // Products, batch by batch; a batch whose products take an operand from
+    // different places is split by source.
     int launch = 2;
-    for (const strassen::Batch &bt : plan.batches) {
+    auto run_batch = [&](size_t bi) -> int {
+        const strassen::Batch &bt = plan.batches[bi];
+        if ((int)bi == chained_batch) {
+            LaunchArgs a;
+            std::memset(&a, 0, sizeof(a));
+            a.C = c.C;
+            a.ldc = c.ldc;
+            a.sm = (int32_t)sm;
+            a.sn = (int32_t)sn;
+            a.sk = (int32_t)sk;
+            a.alpha = c.alpha;
+            a.beta = c.beta;
+            a.tiles_m = (int32_t)((sm + 255) / 256);
+            a.tiles_n = (int32_t)((sn + 255) / 256);
+            const int nchains = (int)bt.products.size();
+            for (int z = 0; z < nchains; ++z) {
+                const int x = bt.products[z];
+                int y = -1;
+                for (size_t q = 0; q < head_of.size(); ++q)
+                    if (head_of[q] == x) y = (int)q;
+                const strassen::Product &px = plan.products[x], &py = plan.products[y];
+                ProductArg &p1 = a.prod[2 * z];
+                ProductArg &p2 = a.prod[2 * z + 1];
+                p1.na = p1.nb = p2.na = p2.nb = 1;
+                p1.nc = px.nc;
+                p2.nc = 1;
+                p1.carry = carry_of[x];
+                set_sources(p1, x);
+                set_sources(p2, y);
+                p1.a[0] = operand_a(x);
+                p1.b[0] = operand_b(x);
+                p2.a[0] = operand_a(y);
+                p2.b[0] = operand_b(y);
+                for (int o = 0; o < px.nc; ++o)
+                    p1.c[o] = c_term(px.c[o], o == carry_of[x] - 1 ? false : first_of(px.c[o].block));
+                p2.c[0] = c_term(py.c[0], first_of(py.c[0].block));
+            }
+            const bool vec = vec_a && vec_b;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            bool timed = false;
+            rc = record_begin(c.stream, &e0, &e1, &timed);
+            if (rc != 0) return rc;
+            const hipError_t err = strassen::launch_m16_chained(fam.op, a, nchains, vec, c.stream);
+            if (err != hipSuccess) return (int)err;
+            if (timed) {
+                char name[64];
+                std::snprintf(name, sizeof(name), "%s<chained,%d,%s>", strassen::m16_kernel_name(fam.op, true),
+                              nchains, vec ? "vec" : "scalar");
+                rc = record_end(c.stream, e0, e1, name, launch, 2 * nchains, a.tiles_m * a.tiles_n * nchains,
+                                2.0 * (double)(2 * nchains) * (double)sm * (double)sn * (double)sk);
+                if (rc != 0) return rc;
+            }
+            ++launch;
+            return 0;
+        }
         for (int pass = 0; pass < 4; ++pass) {
             const bool fa = (pass & 1) != 0, fb = (pass & 2) != 0;
             std::vector<int> sel;
             for (int pi : bt.products)
-                if ((g.a_of[pi] >= 0) == fa && (g.b_of[pi] >= 0) == fb) sel.push_back(pi);
+                if ((g.a_of[pi] >= 0) == fa && (g.b_of[pi] >= 0) == fb && head_of[pi] < 0) sel.push_back(pi);
             if (sel.empty()) continue;
             LaunchArgs a;
             std::memset(&a, 0, sizeof(a));
@@ -749,35 +926,9 @@ int run_formed(const Call &c, void *ws) {
                 pa.na = 1;
                 pa.nb = 1;
                 pa.nc = p.nc;
-                if (fa) {
-                    int64_t rows = 0, cols = 0;
-                    for (int t = 0; t < p.na; ++t) {
-                        rows = std::max(rows, strassen::block_extent(c.m, sm, p.a[t].block / 2));
-                        cols = std::max(cols, strassen::block_extent(c.k, sk, p.a[t].block % 2));
-                    }
-                    pa.a[0] = term((int64_t)g.a_of[pi] * sm * sk, rows, cols, p.a[0].sign, false);
-                } else {
-                    const int R = p.a[0].block / 2, Cc = p.a[0].block % 2;
-                    pa.a[0] = term(R * sm * c.lda + Cc * sk, strassen::block_extent(c.m, sm, R),
-                                   strassen::block_extent(c.k, sk, Cc), p.a[0].sign, false);
-                }
-                if (fb) {
-                    int64_t rows = 0, cols = 0;
-                    for (int t = 0; t < p.nb; ++t) {
-                        rows = std::max(rows, strassen::block_extent(c.k, sk, p.b[t].block / 2));
-                        cols = std::max(cols, strassen::block_extent(c.n, sn, p.b[t].block % 2));
-                    }
-                    pa.b[0] = term((int64_t)g.b_of[pi] * sk * sn, rows, cols, p.b[0].sign, false);
-                } else {
-                    const int R = p.b[0].block / 2, Cc = p.b[0].block % 2;
-                    pa.b[0] = term(R * sk * c.ldb + Cc * sn, strassen::block_extent(c.k, sk, R),
-                                   strassen::block_extent(c.n, sn, Cc), p.b[0].sign, false);
-                }
-                for (int t = 0; t < p.nc; ++t) {
-                    const int R = p.c[t].block / 2, Cc = p.c[t].block % 2;
-                    pa.c[t] = term(R * sm * c.ldc + Cc * sn, strassen::block_extent(c.m, sm, R),
-                                   strassen::block_extent(c.n, sn, Cc), p.c[t].sign, p.c_first[t]);
-                }
+                pa.a[0] = operand_a(pi);
+                pa.b[0] = operand_b(pi);
+                for (int t = 0; t < p.nc; ++t) pa.c[t] = c_term(p.c[t], first_of(p.c[t].block));
             }
             const bool vec = (fa || vec_a) && (fb || vec_b);
             hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -799,7 +950,57 @@ int run_formed(const Call &c, void *ws) {
             }
             ++launch;
         }
+        return 0;
+    };
+
+    // Where chains apply, the batches whose products all take B as stored go
+    // first and B's form runs on the side stream beside them (the form
+    // kernel's waves fit next to the product workgroups: no LDS, few
+    // registers); the caller's stream waits for it before the batches that
+    // read it.  Measured at 8192^3, bf16x3: chains alone gave 0.992x the
+    // plain product's rate, chains and this 1.012x (forming only the early
+    // batches' A sums first and the rest beside them changed nothing more).
+    std::vector<size_t> early, late;
+    for (size_t bi = 0; bi < plan.batches.size(); ++bi) {
+        bool b_formed = false;
+        for (int pi : plan.batches[bi].products) {
+            b_formed = b_formed || g.b_of[pi] >= 0;
+            if (head_of[pi] >= 0) b_formed = b_formed || g.b_of[head_of[pi]] >= 0;
+        }
+        if ((int)bi == chained_batch)
+            for (size_t q = 0; q < head_of.size(); ++q)
+                if (head_of[q] >= 0) b_formed = b_formed || g.b_of[q] >= 0;
+        (b_formed ? late : early).push_back(bi);
     }
+    SideStream *ss = nullptr;
+    // (only together with the chains: where neither applies, the launch
+    // order, and so the result, is the fused schedule's)
+    if (side && fam.m16 && chained_batch >= 0 && !early.empty() && !g.bsums.empty()) {
+        const hipError_t err = side_stream(c.stream, &ss);
+        if (err != hipSuccess) return (int)err;
+    }
+    if (ss != nullptr) {
+        rc = form_operand(g.asums, fe, in_es, c.A, c.lda, c.m, c.k, sm, sk, wa, vec_a, c.stream, 0);
+        if (rc != 0) return rc;
+        hipError_t err = hipEventRecord(ss->fork, c.stream);
+        if (err == hipSuccess) err = hipStreamWaitEvent(ss->s, ss->fork, 0);
+        if (err != hipSuccess) return (int)err;
+        rc = form_operand(g.bsums, fe, in_es, c.B, c.ldb, c.k, c.n, sk, sn, wb, vec_b, ss->s, 1);
+        if (rc != 0) return rc;
+        if ((err = hipEventRecord(ss->join, ss->s)) != hipSuccess) return (int)err;
+        for (size_t bi : early)
+            if ((rc = run_batch(bi)) != 0) return rc;
+        if ((err = hipStreamWaitEvent(c.stream, ss->join, 0)) != hipSuccess) return (int)err;
+        for (size_t bi : late)
+            if ((rc = run_batch(bi)) != 0) return rc;
+        return 0;
+    }
+    rc = form_operand(g.asums, fe, in_es, c.A, c.lda, c.m, c.k, sm, sk, wa, vec_a, c.stream, 0);
+    if (rc != 0) return rc;
+    rc = form_operand(g.bsums, fe, in_es, c.B, c.ldb, c.k, c.n, sk, sn, wb, vec_b, c.stream, 1);
+    if (rc != 0) return rc;
+    for (size_t bi = 0; bi < plan.batches.size(); ++bi)
+        if ((rc = run_batch(bi)) != 0) return rc;
     return 0;
 }
 
@@ -978,7 +1179,7 @@ int strassen_gemm_formed_noalloc(int64_t m, int64_t n, int64_t k, const void *A,
         void *scratch = nullptr;
         const hipError_t err = strassen::noalloc_scratch(c.stream, &scratch);
         if (err != hipSuccess) return (int)err;
-        return run_formed(c, scratch);
+        return run_formed(c, scratch, false);
     } catch (...) {
         return (int)hipErrorOutOfMemory;
     }

@@ -35,6 +35,15 @@ hipError_t launch_m16(Operand16 op, bool trans_a, bool trans_b, bool large, int 
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_m16_chained(Operand16 op, const LaunchArgs &a, int nchains, bool vec, hipStream_t s) {
+    switch (op) {
+        case Operand16::kBf16: return launch_m16_bf16_chained(a, nchains, vec, s);
+        case Operand16::kF16: return launch_m16_f16_chained(a, nchains, vec, s);
+        case Operand16::kBf16x3: return launch_m16_bf16x3_chained(a, nchains, vec, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 const char *m16_kernel_name(Operand16 op, bool large) {
     switch (op) {
         case Operand16::kBf16: return large ? "strassen_m16_kernel<bf16,256x256>" : "strassen_m16_kernel<bf16,128x128>";

@@ -199,7 +199,13 @@ __device__ __forceinline__ typename Ops::Vec load_vec(const typename Ops::In *__
     return v;
 }
 
-template <class C, class Ops, bool A_KC, bool B_KC, int WA, int WB, int WC>
+// CHAIN: a workgroup computes two products of one chain (prod[2z] and
+// prod[2z + 1], single-term operands) into one accumulator: the first
+// product's outputs except the carried one are written after its k loop, the
+// accumulator (negated when the signs require it) then collects the second
+// product, and the sum goes to the carried C block in one update.  A product
+// with a single output thus costs no read-modify-write of C of its own.
+template <class C, class Ops, bool A_KC, bool B_KC, int WA, int WB, int WC, bool CHAIN = false>
 __global__ __launch_bounds__(C::THREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void strassen_m16_kernel(const LaunchArgs args, const int vec) {
     using In = typename Ops::In;
@@ -211,11 +217,6 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
     __shared__ __attribute__((aligned(16))) unsigned short As[2][NPLANES][SA::SIZE];
     __shared__ __attribute__((aligned(16))) unsigned short Bs[2][NPLANES][SB::SIZE];
 
-    const ProductArg &P = args.prod[blockIdx.z];
-    const In *__restrict__ A = static_cast<const In *>(args.A);
-    const In *__restrict__ B = static_cast<const In *>(args.B);
-    const int64_t lda = args.lda, ldb = args.ldb;
-
     int tm, tn;
     tile_coords<C::GROUP>(args.tiles_m, args.tiles_n, tm, tn);
     const int row0 = tm * C::MT, col0 = tn * C::NT;
@@ -224,6 +225,22 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wm = wave % C::WAVES_M, wn = wave / C::WAVES_M;
+
+    f32x16 acc[C::BM][C::BN];
+#pragma unroll
+    for (int i = 0; i < C::BM; ++i)
+#pragma unroll
+        for (int j = 0; j < C::BN; ++j) acc[i][j] = f32x16{};
+
+    // One product into acc, then its epilogue (phase 1 of a chain: all
+    // outputs but the carried one).
+    auto product = [&](const ProductArg &P, const int phase) __attribute__((always_inline)) {
+    const In *__restrict__ A = static_cast<const In *>(P.a_base ? P.a_base : args.A);
+    const In *__restrict__ B = static_cast<const In *>(P.b_base ? P.b_base : args.B);
+    const int64_t lda = P.a_base ? P.lda : args.lda;
+    const int64_t ldb = P.b_base ? P.ldb : args.ldb;
+    const int nc = CHAIN ? P.nc : WC;  // outputs in use
+    const int skip = phase == 1 ? P.carry - 1 : -1;
 
     // Extents shared by every term: x (m for A, n for B) and k.
     int a_x, a_k, b_k, b_x;
@@ -555,12 +572,6 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
 
     auto stage_store = [&](int buf) __attribute__((always_inline)) { stage_store_from(buf, raw_a, raw_b); };
 
-    f32x16 acc[C::BM][C::BN];
-#pragma unroll
-    for (int i = 0; i < C::BM; ++i)
-#pragma unroll
-        for (int j = 0; j < C::BN; ++j) acc[i][j] = f32x16{};
-
     // In MFMA step s of a k-tile, lanes 0-31 supply k = 16s + 0..7 and lanes
     // 32-63 supply k = 16s + 8..15, for A and B alike.
     const int h = lane >> 5, l32 = lane & 31;
@@ -876,17 +887,22 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
     // Epilogue: as in the fp32 kernel (same 32x32 accumulator layout); each
     // accumulator element is scattered to all outputs before the next one.
     float *__restrict__ Cm = args.C;
-    const int64_t ldc = args.ldc;
+    int64_t ldc = args.ldc;
+    // The two epilogues of a chain address the same C tile: an opaque copy
+    // of ldc keeps their addresses from being computed once and held (in
+    // spilled registers) across the second k loop.
+    if constexpr (CHAIN) asm volatile("" : "+s"(ldc));
     const float alpha = args.alpha, beta = args.beta;
     float g[WC];
     int64_t coff[WC];
     int crows[WC], ccols[WC], cfirst[WC];
 #pragma unroll
     for (int o = 0; o < WC; ++o) {
+        const bool used = o < nc && o != skip;  // an unused output is an empty block
         g[o] = P.c[o].sign * (sa0 * sb0) * alpha;
         coff[o] = P.c[o].off;
-        crows[o] = P.c[o].rows;
-        ccols[o] = P.c[o].cols;
+        crows[o] = used ? P.c[o].rows : 0;
+        ccols[o] = used ? P.c[o].cols : 0;
         cfirst[o] = P.c[o].first;
     }
     // Interior tiles (every output block covers the whole tile): no
@@ -895,7 +911,7 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
     bool c_full = true;
 #pragma unroll
     for (int o = 0; o < WC; ++o)
-        c_full = c_full && row0 + C::MT <= crows[o] && col0 + C::NT <= ccols[o];
+        c_full = c_full && (crows[o] == 0 || (row0 + C::MT <= crows[o] && col0 + C::NT <= ccols[o]));
     // With up to two outputs on 256-wide tiles the reads of the next 32x32
     // block are issued before the stores of the current one (the staging
     // registers are free after the k loop), so one block's read latency
@@ -913,7 +929,7 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
         auto cload = [&](int b) __attribute__((always_inline)) {
 #pragma unroll
             for (int o = 0; o < WC; ++o) {
-                if (cfirst[o] && beta == 0.f) continue;
+                if (crows[o] == 0 || (cfirst[o] && beta == 0.f)) continue;
                 const float *pc = cptr(b, o);
 #pragma unroll
                 for (int r = 0; r < 16; ++r) cv[b & 1][o][r] = pc[(int64_t)(8 * (r >> 2) + (r & 3)) * ldc];
@@ -926,6 +942,7 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
             const int i = b / C::BN, j = b % C::BN;
 #pragma unroll
             for (int o = 0; o < WC; ++o) {
+                if (crows[o] == 0) continue;
                 float *pc = cptr(b, o);
                 const bool read = !(cfirst[o] && beta == 0.f);
                 const float cb = cfirst[o] ? beta : 1.f;
@@ -947,6 +964,7 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
                 const int ci0 = row0 + wm * C::WM + i * 32 + 4 * h;
 #pragma unroll
                 for (int o = 0; o < WC; ++o) {
+                    if (crows[o] == 0) continue;
                     float *pc = Cm + coff[o] + (int64_t)ci0 * ldc + cj;
                     const bool read = !(cfirst[o] && beta == 0.f);
                     const float cb = cfirst[o] ? beta : 1.f;
@@ -991,6 +1009,42 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
             }
             __builtin_amdgcn_sched_barrier(0);
         }
+    };
+
+    if constexpr (CHAIN) {
+        const ProductArg &P1 = args.prod[2 * blockIdx.z];
+        const ProductArg &P2 = args.prod[2 * blockIdx.z + 1];
+        product(P1, 1);
+        // acc = s1 M1 (s = product of the first-term signs); the carried block
+        // needs c1 M1 + c2 M2 and the second epilogue scales by c2 s2, so acc
+        // is negated when c1 s1 != c2 s2.  The barrier keeps the second
+        // product's staging stores behind the first one's last LDS reads.
+        const TermArg &out1 = P1.c[P1.carry - 1];
+        const float k1 = out1.sign * P1.a[0].sign * P1.b[0].sign;
+        const float k2 = P2.c[0].sign * P2.a[0].sign * P2.b[0].sign;
+        if (k1 != k2)
+#pragma unroll
+            for (int i = 0; i < C::BM; ++i)
+#pragma unroll
+                for (int j = 0; j < C::BN; ++j) acc[i][j] = -acc[i][j];
+        __syncthreads();
+        product(P2, 2);
+    } else {
+        product(args.prod[blockIdx.z], 0);
+    }
+}
+
+// Chained launch (CHAIN): nchains workgroup grids of two single-term
+// products each, prod[2z] carrying output prod[2z].carry - 1 into
+// prod[2z + 1], whose single output is that same C block.
+template <class C, class Ops>
+hipError_t launch_chained(const LaunchArgs &a, int nchains, bool vec, hipStream_t s) {
+    if (nchains < 1 || 2 * nchains > kMaxBatchArgs) return hipErrorInvalidValue;
+    const dim3 grid(a.tiles_m * a.tiles_n, 1, nchains);
+    const dim3 block(C::THREADS);
+    hipLaunchKernelGGL((strassen_m16_kernel<C, Ops, true, false, 1, 1, 2, true>), grid, block, 0, s, a,
+                       vec ? 1 : 0);
+    return hipGetLastError();
 }
 
 template <class C, class Ops, bool A_KC, bool B_KC, int WA, int WB, int WC>

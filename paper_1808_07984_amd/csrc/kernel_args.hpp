@@ -24,8 +24,15 @@ struct ProductArg {
     TermArg a[4];
     TermArg b[4];
     TermArg c[4];
+    // Operand sources of this product when set (16-bit kernels): its A terms
+    // index a_base with leading dimension lda, its B terms b_base with ldb;
+    // null: LaunchArgs::A / lda (B / ldb).
+    const void *a_base;
+    const void *b_base;
+    int64_t lda, ldb;
     int32_t na, nb, nc;  // terms in use (kernels compiled for a variant use all)
-    int32_t pad;
+    int32_t carry;       // chained launches: 1 + the output this product leaves in the
+                         // accumulator for the next product of its chain; 0 = none
 };
 
 struct LaunchArgs {

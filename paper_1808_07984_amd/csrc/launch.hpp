@@ -55,6 +55,14 @@ STRASSEN_M16_DECL(launch_m16_bf16x3_nt)
 STRASSEN_M16_DECL(launch_m16_bf16x3_tn)
 STRASSEN_M16_DECL(launch_m16_bf16x3_tt)
 #undef STRASSEN_M16_DECL
+// Chained launch of single-term products on 256x256 tiles, A and B as stored:
+// nchains chains of two products (a.prod[2z] carries its output
+// a.prod[2z].carry - 1 into a.prod[2z + 1], whose one output is the same C
+// block), one workgroup grid per chain.
+hipError_t launch_m16_chained(Operand16 op, const LaunchArgs &a, int nchains, bool vec, hipStream_t s);
+hipError_t launch_m16_bf16_chained(const LaunchArgs &a, int nchains, bool vec, hipStream_t s);
+hipError_t launch_m16_f16_chained(const LaunchArgs &a, int nchains, bool vec, hipStream_t s);
+hipError_t launch_m16_bf16x3_chained(const LaunchArgs &a, int nchains, bool vec, hipStream_t s);
 
 // Hybrid top level: out[r][c] = sum_t sign_t * src_t[r * ld_src + c], zero
 // where r >= rows_t or c >= cols_t; out is rows x cols (cols % 4 == 0) with

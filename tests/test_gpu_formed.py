@@ -5,9 +5,12 @@ then single-term products scattered into C.
 * integer inputs: equal to the classical product bit for bit (oracle);
 * real inputs: equal bit for bit to the fused one-level call
   (strassen_gemm_ex, levels = 1), whose sums are formed in the same order
-  and precision, and within tau_1 of the fp64 oracle at the gate eps of the
-  format (bf16x3 at 2^-16: hi + lo carries 16 significant bits; its figure
-  at 2^-23 is printed, not gated);
+  and precision, where no chain applies (fp32, and 16-bit C blocks of fewer
+  than 128 tiles of 256 x 256); with chains (M5 and M6 accumulated after M2
+  and M3 and added into C with them) C0 and C3 may differ in the last bits
+  and C1, C2 stay equal; always within tau_1 of the fp64 oracle at the gate
+  eps of the format (bf16x3 at 2^-16: hi + lo carries 16 significant bits;
+  its figure at 2^-23 is printed, not gated);
 * the library allocates nothing; the workspace is the caller's.
 """
 import numpy as np
@@ -16,7 +19,7 @@ import torch
 
 import oracle
 import paper_1808_07984_amd as sg
-from parity import EPS, e_norm, make_problem, tau, to_device
+from parity import EPS, e_norm, make_problem, stratified_entries, tau, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -79,6 +82,37 @@ def test_formed_equals_fused_one_level(fam, kind, m, n, k):
     assert en <= tau(1)
 
 
+@pytest.mark.parametrize("fam", ["bf16", "f16", "bf16x3"])
+@pytest.mark.parametrize("kind", ["integers", "uniform"])
+def test_formed_chained_16bit(fam, kind):
+    """C blocks of 16 x 8 tiles of 256 x 256: M5 and M6 run chained after M2
+    and M3.  Integers: exact.  Reals: C1 and C2 (not chained) equal the fused
+    call bit for bit; C0 and C3 within a few roundings of it; all within
+    tau_1 of the oracle."""
+    dtype, mode = FAMILIES[fam]
+    m, n, k = 8192, 4096, 1024
+    prob = make_problem(m, n, k, kind=kind, dtype=dtype, c_kind=kind, int_range=(-1, 1))
+    d1, d2 = to_device(prob), to_device(prob)
+    got = _formed(d1, 1.0, 1.0, mode)
+    if kind == "integers":
+        rows, cols = stratified_entries(m, n, 1, 7)
+        want = oracle.gemm_entries(prob["A"], prob["B"], prob["C"], rows, cols, 1.0, 1.0)
+        g = got[torch.as_tensor(rows, device="cuda"), torch.as_tensor(cols, device="cuda")].cpu().double().numpy()
+        assert np.array_equal(g, want)
+        return
+    sg.gemm(d2["A"], d2["B"], d2["C"], levels=1, mode=mode)
+    torch.cuda.synchronize()
+    ref = d2["C"]
+    hm, hn = m // 2, n // 2
+    assert torch.equal(got[:hm, hn:], ref[:hm, hn:])      # C1
+    assert torch.equal(got[hm:, :hn], ref[hm:, :hn])      # C2
+    diff = float((got - ref).abs().max())
+    scale = k * float(prob["A"].float().abs().max()) * float(prob["B"].float().abs().max()) + \
+        float(prob["C"].abs().max())
+    print("chained vs fused: max |diff| %.3g = %.3g of eps scale" % (diff, diff / (GATE_EPS[fam] * scale)), flush=True)
+    assert diff <= tau(1) * GATE_EPS[fam] * scale
+
+
 def test_formed_beta_zero_ignores_nan_and_degenerate():
     prob = make_problem(130, 140, 150, kind="uniform", c_kind="uniform")
     dev = to_device(prob)
@@ -128,8 +162,8 @@ def test_formed_no_device_allocation_and_stream():
 
 @pytest.mark.parametrize("size", [8192, 16384])
 def test_formed_full_size_bf16x3_equals_fused(size):
-    """Benchmark sizes: the whole C equals the fused one-level result, and
-    sampled entries (one per 256 x 256 tile of every C block, plus corners)
+    """Benchmark sizes: C1 and C2 equal the fused one-level result (C0 and
+    C3 take the chained products), and sampled entries (one per 256 x 256 tile of every C block, plus corners)
     are within tau_1 of the fp64 oracle at the bf16x3 gate (2^-16); the
     figure at 2^-23 is printed."""
     m = n = k = size
@@ -142,7 +176,8 @@ def test_formed_full_size_bf16x3_equals_fused(size):
     del C0
     sg.gemm(d1["A"], d1["B"], d1["C"], levels=1, mode="bf16x3")
     torch.cuda.synchronize()
-    assert torch.equal(got, d1["C"])
+    h = size // 2  # chained products add into C0 and C3 only
+    assert torch.equal(got[:h, h:], d1["C"][:h, h:]) and torch.equal(got[h:, :h], d1["C"][h:, :h])
     rng = np.random.default_rng(size)
     ti = np.arange(0, m, 256)
     tj = np.arange(0, n, 256)
