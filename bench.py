@@ -549,8 +549,9 @@ def differentiation_section(steps, dev, stream, log):
 
 def small_sizes_section(steps, dev, stream, log):
     """Small and medium squares (the regime where the paper launches products
-    concurrently with atomic updates): effective TFLOP/s of the batched and
-    the concurrent schedules at one and two levels, and of the plain GEMM."""
+    concurrently): effective TFLOP/s of the batched, the concurrent (atomic
+    updates) and, at one level, the stream-by-stage schedules, and of the
+    plain GEMM."""
     import torch
     import paper_1808_07984_amd as sg
     from paper_1808_07984_amd import inputs
@@ -564,6 +565,7 @@ def small_sizes_section(steps, dev, stream, log):
         for name, L, sched in (("L0", 0, sg.STRASSEN_SCHEDULE_BATCHED),
                                ("L1_batched", 1, sg.STRASSEN_SCHEDULE_BATCHED),
                                ("L1_concurrent", 1, sg.STRASSEN_SCHEDULE_CONCURRENT),
+                               ("L1_streams", 1, sg.STRASSEN_SCHEDULE_STREAMS),
                                ("L2_batched", 2, sg.STRASSEN_SCHEDULE_BATCHED),
                                ("L2_concurrent", 2, sg.STRASSEN_SCHEDULE_CONCURRENT)):
             sg.strassen_set_schedule(sched)

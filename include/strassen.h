@@ -228,10 +228,20 @@ int strassen_set_tile(int tile);
  *   hardware fp32 atomic add, which needs C in ordinary (coarse-grained)
  *   device memory: with C in fine-grained or host-coherent memory the
  *   concurrent schedule is not supported.
+ * STREAMS (table "tab:gpu_streaming"): one-level calls only (strassen_gemm,
+ *   strassen_gemm_ex; other calls keep the batched schedule): each product
+ *   is one launch, on the call's stream or on a second stream of the calling
+ *   thread (created on first use, default priority) as the table assigns it;
+ *   products of one stage run at once on the two streams, and each stage
+ *   waits for the previous one on both, so every C element is updated in a
+ *   fixed order (deterministic; the order differs from BATCHED's, so the
+ *   last bits can differ).  The call's stream waits for the second stream
+ *   before the call returns.
  * Applies to the calling thread's later calls only; returns 0 or -1 (bad
  * value). */
 #define STRASSEN_SCHEDULE_BATCHED 0
 #define STRASSEN_SCHEDULE_CONCURRENT 1
+#define STRASSEN_SCHEDULE_STREAMS 2
 int strassen_set_schedule(int schedule);
 
 /* Description of how a call of this shape is executed. */

@@ -26,6 +26,7 @@ from ._binding import (  # noqa: F401
     STRASSEN_MODE_PLAIN,
     STRASSEN_SCHEDULE_BATCHED,
     STRASSEN_SCHEDULE_CONCURRENT,
+    STRASSEN_SCHEDULE_STREAMS,
     STRASSEN_TILE_128,
     STRASSEN_TILE_256,
     STRASSEN_TILE_AUTO,

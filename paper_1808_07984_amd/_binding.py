@@ -213,7 +213,7 @@ def strassen_set_tile(tile):
     return lib.strassen_set_tile(tile)
 
 
-STRASSEN_SCHEDULE_BATCHED, STRASSEN_SCHEDULE_CONCURRENT = 0, 1
+STRASSEN_SCHEDULE_BATCHED, STRASSEN_SCHEDULE_CONCURRENT, STRASSEN_SCHEDULE_STREAMS = 0, 1, 2
 
 
 def strassen_set_schedule(schedule):

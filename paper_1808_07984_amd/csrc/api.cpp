@@ -295,6 +295,75 @@ int run_concurrent(const Call &c, const Plan &plan, bool vec) {
     return 0;
 }
 
+// Starts the launch record of one kernel when recording is on.
+int record_begin(hipStream_t s, hipEvent_t *e0, hipEvent_t *e1, bool *timed) {
+    Recorder &rec = recorder();
+    *timed = false;
+    {
+        std::lock_guard<std::mutex> lk(rec.mu);
+        if (!rec.on) return 0;
+        hipError_t e = rec.take(e0);
+        if (e == hipSuccess) e = rec.take(e1);
+        if (e != hipSuccess) return (int)e;
+    }
+    *timed = true;
+    return (int)hipEventRecord(*e0, s);
+}
+
+int record_end(hipStream_t s, hipEvent_t e0, hipEvent_t e1, const char *kernel, int launch, int batch,
+               int workgroups, double flops) {
+    const hipError_t err = hipEventRecord(e1, s);
+    if (err != hipSuccess) return (int)err;
+    Record r;
+    std::memset(&r.info, 0, sizeof(r.info));
+    std::snprintf(r.info.kernel, sizeof(r.info.kernel), "%s", kernel);
+    r.info.launch = launch;
+    r.info.batch = batch;
+    r.info.workgroups = workgroups;
+    r.info.flops = flops;
+    r.e0 = e0;
+    r.e1 = e1;
+    Recorder &rec = recorder();
+    std::lock_guard<std::mutex> lk(rec.mu);
+    rec.recs.push_back(r);
+    ++rec.total;
+    return 0;
+}
+
+// A second stream of the calling thread on one device, with a fork and a
+// join event, on which the formed schedule runs B's form beside the product
+// launches that need no formed B operand.  Created on first use (default
+// priority, non-blocking) and kept until the thread ends.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+constexpr int kSideDevices = 64;
+thread_local SideStream g_side[kSideDevices];
+
+hipError_t side_stream(hipStream_t caller, SideStream **out) {
+    int dev = 0;
+    hipError_t err = caller ? hipStreamGetDevice(caller, &dev) : hipGetDevice(&dev);
+    if (err != hipSuccess) return err;
+    if (dev < 0 || dev >= kSideDevices) return hipErrorInvalidDevice;
+    SideStream &ss = g_side[dev];
+    if (ss.s == nullptr) {
+        int cur = 0;
+        if ((err = hipGetDevice(&cur)) != hipSuccess) return err;
+        if (cur != dev && (err = hipSetDevice(dev)) != hipSuccess) return err;
+        err = hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking);
+        if (err == hipSuccess) err = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming);
+        if (err == hipSuccess) err = hipEventCreateWithFlags(&ss.join, hipEventDisableTiming);
+        const hipError_t back = cur != dev ? hipSetDevice(cur) : hipSuccess;
+        if (err != hipSuccess) return err;
+        if (back != hipSuccess) return back;
+    }
+    *out = &ss;
+    return hipSuccess;
+}
+
+int run_streams(const Call &c, const Plan &plan, const Family &fam, bool vec);
+
 int run(const Call &c) {
     if (c.m == 0 || c.n == 0) return 0;
     if (c.k == 0 || c.alpha == 0.f)
@@ -328,6 +397,7 @@ int run(const Call &c) {
     if (g_schedule == STRASSEN_SCHEDULE_CONCURRENT && !fam.m16 &&
         !c.trans_a && !c.trans_b && c.levels > 0)
         return run_concurrent(c, plan, vec);
+    if (g_schedule == STRASSEN_SCHEDULE_STREAMS && c.levels == 1) return run_streams(c, plan, fam, vec);
 
     Recorder &rec = recorder();
     for (size_t bi = 0; bi < plan.batches.size(); ++bi) {
@@ -410,6 +480,100 @@ int run(const Call &c) {
             ++rec.total;
         }
     }
+    return 0;
+}
+
+// Stream-by-stage schedule (Task Parallelism section, table tab:gpu_streaming):
+// each one-level product is one launch, on the caller's stream (0) or the
+// side stream (1) as the table assigns it; the products of a stage run at
+// once, and each stage waits for the previous one on both streams (the two
+// streams of a stage write disjoint C quadrants).  Beta is applied by the
+// first update of each quadrant in this order.
+int run_streams(const Call &c, const Plan &plan, const Family &fam, bool vec) {
+    SideStream *ss = nullptr;
+    hipError_t err = side_stream(c.stream, &ss);
+    if (err != hipSuccess) return (int)err;
+    const std::vector<strassen::Product> all = strassen::scheme(1);
+    const std::vector<strassen::StreamSlot> slots = strassen::stream_stages();
+    bool touched[4] = {false, false, false, false};
+    // the side stream starts after the caller's earlier work
+    if ((err = hipEventRecord(ss->fork, c.stream)) != hipSuccess) return (int)err;
+    if ((err = hipStreamWaitEvent(ss->s, ss->fork, 0)) != hipSuccess) return (int)err;
+    int stage = 0;
+    for (size_t i = 0; i < slots.size(); ++i) {
+        const strassen::StreamSlot &sl = slots[i];
+        if (sl.stage != stage) {
+            // stage barrier: each stream waits for the other's work so far
+            if ((err = hipEventRecord(ss->fork, c.stream)) != hipSuccess) return (int)err;
+            if ((err = hipEventRecord(ss->join, ss->s)) != hipSuccess) return (int)err;
+            if ((err = hipStreamWaitEvent(c.stream, ss->join, 0)) != hipSuccess) return (int)err;
+            if ((err = hipStreamWaitEvent(ss->s, ss->fork, 0)) != hipSuccess) return (int)err;
+            stage = sl.stage;
+        }
+        const strassen::Product &p = all[sl.product];
+        const hipStream_t s = sl.stream == 0 ? c.stream : ss->s;
+        LaunchArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.A = c.A;
+        a.B = c.B;
+        a.C = c.C;
+        a.lda = c.lda;
+        a.ldb = c.ldb;
+        a.ldc = c.ldc;
+        a.sm = (int32_t)plan.sm;
+        a.sn = (int32_t)plan.sn;
+        a.sk = (int32_t)plan.sk;
+        a.alpha = c.alpha;
+        a.beta = c.beta;
+        a.trans_a = c.trans_a;
+        a.trans_b = c.trans_b;
+        const bool large = use_large(plan.sm, plan.sn, plan.sk, 1, !fam.m16);
+        const strassen::KernelShape ks = shape_of(fam, large, p.na, p.nb, p.nc, !c.trans_a && !c.trans_b);
+        a.tiles_m = (int32_t)((plan.sm + ks.mt - 1) / ks.mt);
+        a.tiles_n = (int32_t)((plan.sn + ks.nt - 1) / ks.nt);
+        ProductArg &pa = a.prod[0];
+        pa.na = p.na;
+        pa.nb = p.nb;
+        pa.nc = p.nc;
+        for (int t = 0; t < p.na; ++t) {
+            const int R = p.a[t].block / 2, Cc = p.a[t].block % 2;
+            const int64_t off = c.trans_a ? Cc * plan.sk * c.lda + R * plan.sm : R * plan.sm * c.lda + Cc * plan.sk;
+            pa.a[t] = term(off, strassen::block_extent(c.m, plan.sm, R), strassen::block_extent(c.k, plan.sk, Cc),
+                           p.a[t].sign, false);
+        }
+        for (int t = 0; t < p.nb; ++t) {
+            const int R = p.b[t].block / 2, Cc = p.b[t].block % 2;
+            const int64_t off = c.trans_b ? Cc * plan.sn * c.ldb + R * plan.sk : R * plan.sk * c.ldb + Cc * plan.sn;
+            pa.b[t] = term(off, strassen::block_extent(c.k, plan.sk, R), strassen::block_extent(c.n, plan.sn, Cc),
+                           p.b[t].sign, false);
+        }
+        for (int t = 0; t < p.nc; ++t) {
+            const int blk = p.c[t].block, R = blk / 2, Cc = blk % 2;
+            pa.c[t] = term(R * plan.sm * c.ldc + Cc * plan.sn, strassen::block_extent(c.m, plan.sm, R),
+                           strassen::block_extent(c.n, plan.sn, Cc), p.c[t].sign, !touched[blk]);
+            touched[blk] = true;
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        bool timed = false;
+        int rc = record_begin(s, &e0, &e1, &timed);
+        if (rc != 0) return rc;
+        err = fam.m16 ? strassen::launch_m16(fam.op, c.trans_a != 0, c.trans_b != 0, large, p.na, p.nb, p.nc, a, 1,
+                                             vec, s)
+                      : strassen::launch_f32(c.trans_a != 0, c.trans_b != 0, large, p.na, p.nb, p.nc, a, 1, vec, s);
+        if (err != hipSuccess) return (int)err;
+        if (timed) {
+            char name[64];
+            std::snprintf(name, sizeof(name), "%s<%d,%d,%d,stream %d>",
+                          fam.m16 ? strassen::m16_kernel_name(fam.op, large) : strassen::f32_kernel_name(large),
+                          p.na, p.nb, p.nc, sl.stream);
+            rc = record_end(s, e0, e1, name, (int)i, 1, a.tiles_m * a.tiles_n,
+                            2.0 * (double)plan.sm * (double)plan.sn * (double)plan.sk);
+            if (rc != 0) return rc;
+        }
+    }
+    // the caller's stream waits for the side stream's last work
+    if ((err = hipEventRecord(ss->join, ss->s)) != hipSuccess) return (int)err;
+    if ((err = hipStreamWaitEvent(c.stream, ss->join, 0)) != hipSuccess) return (int)err;
     return 0;
 }
 
@@ -621,41 +785,6 @@ FormedGeom formed_geom(int64_t m, int64_t n, int64_t k, const Family &fam) {
     return g;
 }
 
-// Starts the launch record of one kernel when recording is on.
-int record_begin(hipStream_t s, hipEvent_t *e0, hipEvent_t *e1, bool *timed) {
-    Recorder &rec = recorder();
-    *timed = false;
-    {
-        std::lock_guard<std::mutex> lk(rec.mu);
-        if (!rec.on) return 0;
-        hipError_t e = rec.take(e0);
-        if (e == hipSuccess) e = rec.take(e1);
-        if (e != hipSuccess) return (int)e;
-    }
-    *timed = true;
-    return (int)hipEventRecord(*e0, s);
-}
-
-int record_end(hipStream_t s, hipEvent_t e0, hipEvent_t e1, const char *kernel, int launch, int batch,
-               int workgroups, double flops) {
-    const hipError_t err = hipEventRecord(e1, s);
-    if (err != hipSuccess) return (int)err;
-    Record r;
-    std::memset(&r.info, 0, sizeof(r.info));
-    std::snprintf(r.info.kernel, sizeof(r.info.kernel), "%s", kernel);
-    r.info.launch = launch;
-    r.info.batch = batch;
-    r.info.workgroups = workgroups;
-    r.info.flops = flops;
-    r.e0 = e0;
-    r.e1 = e1;
-    Recorder &rec = recorder();
-    std::lock_guard<std::mutex> lk(rec.mu);
-    rec.recs.push_back(r);
-    ++rec.total;
-    return 0;
-}
-
 // Forms the sums of one operand X (quadrant (R, Cc) at X + R*srows*ldx +
 // Cc*scols, extents clipped to xr x xc) into `out`, one srows x scols block
 // per sum, dense with leading dimension scols.
@@ -695,38 +824,6 @@ int form_operand(const std::vector<FormedSum> &sums, strassen::FormElem fe, size
         return record_end(s, e0, e1, fe == strassen::FormElem::kF32 ? "form_sums<f32>" : "form_sums<16-bit>",
                           launch, (int)sums.size(), (int)(srows < 65536 ? srows : 65536), 0.0);
     return 0;
-}
-
-// A second stream of the calling thread on one device, with a fork and a
-// join event, on which the formed schedule runs B's form beside the product
-// launches that need no formed B operand.  Created on first use (default
-// priority, non-blocking) and kept until the thread ends.
-struct SideStream {
-    hipStream_t s = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
-};
-constexpr int kSideDevices = 64;
-thread_local SideStream g_side[kSideDevices];
-
-hipError_t side_stream(hipStream_t caller, SideStream **out) {
-    int dev = 0;
-    hipError_t err = caller ? hipStreamGetDevice(caller, &dev) : hipGetDevice(&dev);
-    if (err != hipSuccess) return err;
-    if (dev < 0 || dev >= kSideDevices) return hipErrorInvalidDevice;
-    SideStream &ss = g_side[dev];
-    if (ss.s == nullptr) {
-        int cur = 0;
-        if ((err = hipGetDevice(&cur)) != hipSuccess) return err;
-        if (cur != dev && (err = hipSetDevice(dev)) != hipSuccess) return err;
-        err = hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking);
-        if (err == hipSuccess) err = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming);
-        if (err == hipSuccess) err = hipEventCreateWithFlags(&ss.join, hipEventDisableTiming);
-        const hipError_t back = cur != dev ? hipSetDevice(cur) : hipSuccess;
-        if (err != hipSuccess) return err;
-        if (back != hipSuccess) return back;
-    }
-    *out = &ss;
-    return hipSuccess;
 }
 
 // side: B's form may run on a side stream (creating it on first use);
@@ -1191,7 +1288,8 @@ int strassen_set_stream(void *hip_stream) {
 }
 
 int strassen_set_schedule(int schedule) {
-    if (schedule != STRASSEN_SCHEDULE_BATCHED && schedule != STRASSEN_SCHEDULE_CONCURRENT)
+    if (schedule != STRASSEN_SCHEDULE_BATCHED && schedule != STRASSEN_SCHEDULE_CONCURRENT &&
+        schedule != STRASSEN_SCHEDULE_STREAMS)
         return -1;
     g_schedule = schedule;
     return 0;

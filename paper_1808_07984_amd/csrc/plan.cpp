@@ -91,6 +91,12 @@ std::vector<Product> scheme(int levels) {
     return cur;
 }
 
+std::vector<StreamSlot> stream_stages() {
+    // stage 0: M1, M5 on stream 0 and M4, M6 on stream 1 (M1 and M5 share
+    // C3, M4 and M6 share C0); stage 1: M2 | M3; stage 2: M0.
+    return {{1, 0, 0}, {5, 0, 0}, {4, 0, 1}, {6, 0, 1}, {2, 1, 0}, {3, 1, 1}, {0, 2, 0}};
+}
+
 Plan make_plan(int64_t m, int64_t n, int64_t k, int levels, int vec, bool round_m) {
     Plan p;
     p.levels = levels;

@@ -50,6 +50,18 @@ std::vector<Product> scheme(int levels);
 // levels >= 1, so vector loads stay aligned.
 Plan make_plan(int64_t m, int64_t n, int64_t k, int levels, int vec, bool round_m = false);
 
+// Stream-by-stage schedule of the seven one-level products (Task Parallelism
+// section, table "tab:gpu_streaming"): products of one stage run at once on
+// streams 0 and 1, products on one stream in the listed order, and every
+// stage waits for the previous one on both streams.  Entries are indices
+// into scheme(1) (M0..M6), in launch order.
+struct StreamSlot {
+    int product;
+    int stage;
+    int stream;
+};
+std::vector<StreamSlot> stream_stages();
+
 // Rows (or columns) of block index `b` (0 <= b < d) that lie inside a
 // dimension of size `dim` when blocks have extent `s`:  clamp(dim - b*s, 0, s).
 inline int64_t block_extent(int64_t dim, int64_t s, int b) {
