@@ -61,6 +61,10 @@ def parse():
                    help="skip the bf16x3 plain / fused / formed comparison")
     p.add_argument("--no-small", action="store_true",
                    help="skip the small-size schedule section")
+    p.add_argument("--launch-table", metavar="PATH",
+                   help="only time every launch of squares m=n=k in 1024..16384 at levels 0/1/2 "
+                        "(fp32, bf16, bf16x3; plus the formed one-level calls) with library "
+                        "events and write them to PATH as JSON (for the performance model)")
     return p.parse_args()
 
 
@@ -578,6 +582,62 @@ def small_sizes_section(steps, dev, stream, log):
     return out
 
 
+def launch_table(path, dev, stream, log, sizes=(1024, 2048, 4096, 8192, 16384), reps=3):
+    """Every launch of C := A*B at m=n=k in `sizes`, levels 0/1/2, for fp32,
+    bf16 and bf16x3 (N(0,1) operands, drawn on the device: the 16-bit
+    matrix cores' power-limited clock depends on operand values), plus the
+    formed one-level calls of bf16 and bf16x3: per launch the median over
+    `reps` recorded calls of its library-event time, and the median call
+    time.  Written to `path` as JSON records."""
+    import json
+    import numpy as np
+    import torch
+    import paper_1808_07984_amd as sg
+
+    g = torch.Generator(device=dev)
+    out = []
+    for N in sizes:
+        g.manual_seed(N)
+        Af = torch.randn(N, N, device=dev, generator=g)
+        Bf = torch.randn(N, N, device=dev, generator=g)
+        C = torch.zeros(N, N, device=dev)
+        operands = {"f32": (Af, Bf, "plain"), "bf16": (Af.bfloat16(), Bf.bfloat16(), "plain"),
+                    "x3": (Af, Bf, "bf16x3")}
+        cases = [(kind, L, "fused") for kind in ("f32", "bf16", "x3") for L in (0, 1, 2)]
+        cases += [("bf16", 1, "formed"), ("x3", 1, "formed")]
+        for kind, L, sched in cases:
+            A, B, mode = operands[kind]
+            if sched == "formed":
+                ws = torch.empty(sg.api.formed_workspace_bytes(N, N, N, A.dtype, mode),
+                                 dtype=torch.uint8, device=dev)
+                fn = lambda: sg.gemm_formed(A, B, C, 1.0, 0.0, mode=mode, workspace=ws)
+            else:
+                fn = lambda: sg.gemm(A, B, C, 1.0, 0.0, levels=L, mode=mode)
+            call_ms = [time_calls(fn, 1, 1 if r == 0 else 0, stream) for r in range(reps)]
+            per = {}
+            for _ in range(reps):
+                sg.strassen_profile_start()
+                fn()
+                rc, recs = sg.strassen_profile_stop(capacity=256)
+                if rc < 0:
+                    raise SystemExit("strassen_profile_stop failed: %d" % rc)
+                for i, r in enumerate(recs):
+                    per.setdefault(i, (r, []))[1].append(r.ms)
+            launches = [{"kernel": r.kernel.decode(), "launch": int(r.launch), "batch": int(r.batch),
+                         "workgroups": int(r.workgroups), "ms": round(float(np.median(ms)), 4)}
+                        for i, (r, ms) in sorted(per.items())]
+            out.append({"kind": kind, "N": N, "levels": L, "schedule": sched,
+                        "call_ms": round(float(np.median(call_ms)), 4), "launches": launches})
+            log("%s N=%d L%d %s: %.3f ms, %d launches" % (kind, N, L, sched, out[-1]["call_ms"],
+                                                         len(launches)))
+            if sched == "formed":
+                del ws
+        del Af, Bf, C, operands
+        torch.cuda.empty_cache()
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -593,6 +653,9 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.launch_table:
+        launch_table(args.launch_table, dev, torch.cuda.current_stream(dev), log)
+        return
     N = args.size
     m = n = k = N
     log("generating inputs %dx%d fp32" % (N, N))

@@ -102,8 +102,11 @@ def formed_workspace_bytes(m, n, k, dtype=torch.float32, mode="plain"):
 
 def gemm_formed(A, B_, C, alpha=1.0, beta=1.0, mode="plain", workspace=None, stream=None):
     """One-level Strassen with the two-term operand sums formed first into
-    workspace: C := alpha * A @ B + beta * C in place, bit-identical to
-    gemm(..., levels=1).  A, B: fp32, bf16 or fp16 GPU tensors of one dtype,
+    workspace: C := alpha * A @ B + beta * C in place.  Equal to
+    gemm(..., levels=1) bit for bit, except that on the 16-bit matrix cores
+    with 256x256 tiles the products M5 and M6 are accumulated after M2 and M3
+    and added into C3 and C0 with them, so those two blocks can differ in the
+    last bits.  A, B: fp32, bf16 or fp16 GPU tensors of one dtype,
     as stored (no transposes); C fp32.  `workspace` is a GPU tensor of at
     least formed_workspace_bytes(...) bytes (allocated by torch here when not
     given: the library itself allocates nothing).  Returns C."""

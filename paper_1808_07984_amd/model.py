@@ -4,44 +4,47 @@ The Analysis section of the paper models one kernel as
     T = max(T_flop, T_smop, T_gmop)
 with per-thread-block counts of arithmetic, shared-memory and global-memory
 operations (eqs. n_flop, AB_gr_rs, AB_sr, C_rg) divided by the corresponding
-device throughputs, after choosing the blocking that keeps each ratio below
-the machine balance (eqs. constrain_glb, constrain_sha_bdw).  The same form
-is used here with the gfx950 resources the kernels actually use:
+device throughputs.  The same form is kept here, per workgroup and per round
+of workgroups, with the gfx950 resources the kernels use and throughputs
+measured on MI355X:
 
-  flop   MFMA flops                    / (CUs * MFMA flop/clk/CU * clock)
-  valu   operand-staging VALU ops      / (CUs * 64 lane-ops/clk * clock)
-  lds    LDS bytes written / (CUs * 128 B/clk * clock)
-         + LDS bytes read  / (CUs * 256 B/clk * clock)
-  l2     L2 -> CU operand bytes        / (CUs * L2 B/clk/CU * clock)
-  hbm    algorithmic HBM bytes         / HBM bandwidth
+* a launch of W workgroups on S = CUs x (workgroups per CU) slots runs in
+  rounds of at most S workgroups; a round of w workgroups puts
+  c = ceil(w / CUs) of them on each of min(w, CUs) CUs;
+* one round costs
+      max(c * (T_flop + T_valu), c * T_lds, w/a * T_fetch) + w/a * T_C + T_round
+  per CU, where
+      T_flop   MFMA flops of one workgroup / (MFMA flop/clk/CU * clock)
+      T_valu   operand-staging lane-ops / (64 lane-ops/clk/CU * clock): each
+               wave issues its sums in order with its MFMAs and meets a
+               barrier every k-tile, so staging adds to the MFMA time
+      T_lds    LDS bytes written / 128 B/clk + read / 256 B/clk
+      T_fetch  A-operand bytes / R_A + B-operand bytes / R_B (the operand
+               bytes one workgroup requests over its k loop, every term of
+               every sum counted)
+      T_C      C bytes of the epilogue (a read and a write of 4 bytes per
+               element per output) / R_C: the epilogue follows the k loop,
+               so it adds
+      T_round  a fixed cost per round (pipeline fill at the start of a tile,
+               drain at its end);
+* a launch costs the sum of its rounds, at least its algorithmic HBM bytes
+  over 8 TB/s, plus a launch overhead.
 
-per launch (one race-free batch of products of one variant), with the
-counts of one workgroup tile.  The staging VALU work is added to the MFMA
-time rather than overlapped with it: each wave issues its sums in order with
-its MFMAs and meets a barrier every k-tile, and measured kernels lose about
-the VALU/MFMA ratio (fp32 W > 1 kernels a few per cent; 16-bit one-level
-launches more than the flops they save):
-  operand bytes per k-tile   (W_A * MT + W_B * NT) * KT * b_in        (l2)
-  LDS bytes per k-tile       (MT + NT) * KT * b_lds * planes           (stores)
-                             + waves * (WM + WN) * KT * b_lds * planes (fragment reads)
-  C bytes per tile           2 * 4 * W_C * MT * NT                     (epilogue)
-  staging ops per k-tile     per element of each operand tile: fp32 one
-                             multiply-add per term; 16-bit one pass-through
-                             (single term) or a convert and an FMA per term
-                             plus half a packed rounding; bf16x3 adds the
-                             hi/lo split
-and a wave-quantisation factor ceil(W / S) / (W / S) for W workgroups on S
-slots (the paper's inter-kernel parallelism argument for small problems).
-A launch costs max(T_flop + T_valu, T_lds, T_l2, T_hbm) times that factor,
-plus a fixed launch overhead.  The constants below are public MI355X figures
-or measured on it: the LDS widths with a microbenchmark (16-byte reads 256
-B/clk/CU, 16-byte writes 125), the clock under the fp32 GEMM
-(GRBM_GUI_ACTIVE), and the clock under sustained 16-bit MFMA work on random
-operands, which is power limited (a pure 32x32x16 MFMA loop sustains
-1.69-1.75 PFLOP/s, every instruction still 32 cycles: ~1.65 GHz).  16-bit
-and compensated launches use that clock for every term.  The model leaves
-out load latency and barrier waits, which it therefore underestimates for
-the 16-bit kernels (see the measured MFMA-busy fractions).
+R_A, R_B, R_C, T_round and the 0.9 factor of the 128 x 128 tile's operand
+rates are fitted to the event times of every launch of squares 1024-16384 at
+levels 0/1/2 (fp32, bf16 and the compensated mode).  They are per-CU rates
+of latency-bound loads, not bandwidths: the sixteen-bit kernels reach about
+a third of their MFMA peak on the plain product, and their multi-term launches
+are set by how many operand bytes a CU can keep in flight.  The B operand
+costs about twice the A operand per byte: the eight-XCD tile mapping walks
+groups of four tile rows, so the 32 workgroups one XCD runs at once share
+each A panel eight ways and each B panel only four ways.  Clocks are the
+measured ones: fp32 under the GEMM (GRBM_GUI_ACTIVE), 16-bit under sustained
+MFMA work on random operands, which is power limited (~1.65 GHz).
+
+Also modelled: the formed one-level schedule's sum kernels (streaming, at a
+measured 5 TB/s) and its chained launches (two products per workgroup, one
+epilogue).
 """
 import math
 
@@ -54,18 +57,106 @@ MFMA_FLOP_PER_CLK_CU = {"f32": 256.0, "16bit": 4096.0}
 LDS_WRITE_B_PER_CLK_CU = 128.0
 LDS_READ_B_PER_CLK_CU = 256.0
 VALU_OPS_PER_CLK_CU = 64.0   # 4 SIMDs x 16 lanes
-L2_B_PER_CLK_CU = 64.0
+R_A_B_PER_S_CU = 55e9        # A-operand bytes per second per CU (fitted)
+R_B_B_PER_S_CU = 28e9        # B-operand bytes per second per CU (fitted)
+R_C_B_PER_S_CU = 30e9        # epilogue C bytes per second per CU (fitted)
+SMALL_TILE_FETCH = 0.9       # 128x128 tile: operand time factor (fitted)
+ROUND_S = 4e-6               # fixed cost per round of workgroups (fitted)
+FORM_B_PER_S = 5.0e12        # sum-forming kernels, bytes read + written (measured)
 HBM_B_PER_S = 8.0e12
 LAUNCH_S = 6e-6
 
-TILES = {  # (MT, NT, KT, waves, workgroups per CU)
-    ("f32", False): (128, 128, 32, 4, 2),
-    ("f32", True): (256, 256, 32, 8, 1),   # KT 16 above four operand terms but (4,1,4), (4,2,2)
-    ("16bit", False): (128, 128, 32, 4, 2),
-    ("16bit", True): (256, 256, 64, 8, 1),  # KT 32 above four operand terms and for (1,2,2)
-    ("x3", False): (128, 128, 32, 4, 2),
-    ("x3", True): (256, 256, 16, 8, 1),
-}
+OCCUPANCY = {False: 2, True: 1}   # workgroups per CU: 128x128 (4 waves), 256x256 (8 waves)
+
+
+def tile(kind, large, wa, wb, wc, a_kc=True, b_kc=False):
+    """(MT, NT, KT) the library instantiates for this variant.  kind in
+    {'f32', '16bit', 'x3'}; a_kc / b_kc: A and B k-contiguous in memory
+    (row-major A, row-major B: a_kc True, b_kc False)."""
+    if not large:
+        return 128, 128, 32
+    if kind == "f32":
+        split = a_kc and not b_kc and wa == 4 and (wb, wc) in ((1, 4), (2, 2))
+        return 256, 256, 16 if wa + wb > 4 and not split else 32
+    if kind == "16bit":
+        return 256, 256, 64 if wa + wb <= 4 and (wa, wb) != (1, 2) else 32
+    return 256, 256, 32 if wa + wb == 2 and a_kc and not b_kc else 16
+
+
+def _staging(kind, w):
+    """VALU lane-ops per element of one operand tile for a w-term sum: fp32
+    one multiply-add per term; 16-bit one pass-through (single term) or a
+    convert and an FMA per term plus half a packed rounding; the compensated
+    mode adds the hi/lo split."""
+    if kind == "f32":
+        return float(w)
+    if kind == "x3":
+        return 2.0 * w + 3.0
+    return 0.125 if w == 1 else 2.0 * w + 0.5
+
+
+def launch(kind, large, wa, wb, wc, sm, sn, sk, batch, products_per_workgroup=1):
+    """Predicted seconds of one launch: `batch` products of sm x sk by
+    sk x sn sub-blocks with W_A, W_B, W_C terms, each workgroup running
+    `products_per_workgroup` products in turn (2 for a chained launch) and
+    one epilogue of wc outputs.  Returns a dict of the terms."""
+    mt, nt, kt = tile(kind, large, wa, wb, wc)
+    b_in = 2 if kind == "16bit" else 4
+    b_lds = 4 if kind == "f32" else 2
+    planes = 2 if kind == "x3" else 1
+    mult = 3 if kind == "x3" else 1
+    clock = CLOCK_HZ if kind == "f32" else CLOCK_16BIT_HZ
+    rate = MFMA_FLOP_PER_CLK_CU["f32" if kind == "f32" else "16bit"]
+    waves = 8 if large else 4
+    wm, wn = mt // 2, nt // (waves // 2)
+    ktiles = math.ceil(sk / kt) * products_per_workgroup
+    per_wg = {
+        "flop": 2.0 * mt * nt * kt * ktiles * mult / (rate * clock),
+        "valu": (mt * _staging(kind, wa) + nt * _staging(kind, wb)) * kt * ktiles
+                / (VALU_OPS_PER_CLK_CU * clock),
+        "lds": ((mt + nt) * kt * b_lds * planes / LDS_WRITE_B_PER_CLK_CU
+                + waves * (wm + wn) * kt * b_lds * planes / LDS_READ_B_PER_CLK_CU) * ktiles / clock,
+        "fetch": (wa * mt / R_A_B_PER_S_CU + wb * nt / R_B_B_PER_S_CU) * kt * b_in * ktiles
+                 * (1.0 if large else SMALL_TILE_FETCH),
+        "epilogue": 8.0 * wc * mt * nt / R_C_B_PER_S_CU,
+    }
+    tiles = math.ceil(sm / mt) * math.ceil(sn / nt) * batch
+    slots = CUS * OCCUPANCY[large]
+    full, rest = divmod(tiles, slots)
+    rounds = [slots] * full + ([rest] if rest else [])
+    t = 0.0
+    busy = {"compute": 0.0, "lds": 0.0, "fetch": 0.0}
+    for w in rounds:
+        active = min(w, CUS)
+        per_cu = w / active
+        c = math.ceil(w / CUS)
+        r = {"compute": c * (per_wg["flop"] + per_wg["valu"]), "lds": c * per_wg["lds"],
+             "fetch": per_cu * per_wg["fetch"]}
+        t += max(r.values()) + per_cu * per_wg["epilogue"] + ROUND_S
+        for key in busy:
+            busy[key] += r[key]
+    hbm = batch * (b_in * (wa * sm * sk + wb * sk * sn) * products_per_workgroup
+                   + 8 * wc * sm * sn) / HBM_B_PER_S
+    bound = max(busy, key=busy.get)
+    if bound == "compute":
+        bound = "flop" if per_wg["flop"] >= per_wg["valu"] else "valu"
+    if hbm > t:
+        t, bound = hbm, "hbm"
+    flops_total = 2.0 * mt * nt * kt * ktiles * mult * tiles
+    return {"variant": (wa, wb, wc), "batch": batch, "tile": (mt, nt, kt), "workgroups": tiles,
+            "rounds": len(rounds), "bound": bound, "seconds": t + LAUNCH_S,
+            "t_flop": flops_total / (CUS * rate * clock),
+            "t_valu": per_wg["valu"] * tiles / CUS,
+            "t_fetch": per_wg["fetch"] * tiles / CUS,
+            "t_epilogue": per_wg["epilogue"] * tiles / CUS,
+            "t_hbm": hbm}
+
+
+def form(kind, rows, cols, n_sources, n_sums):
+    """Seconds of one sum-forming launch: n_sources source blocks read once,
+    n_sums sums of rows x cols written, streaming."""
+    es = 2 if kind == "16bit" else 4
+    return es * rows * cols * (n_sources + n_sums) / FORM_B_PER_S + LAUNCH_S
 
 
 def _batches(levels):
@@ -94,7 +185,7 @@ def _use_large(sm, sn, sk, batch, f32):
 
 
 def predict(m, n, k, levels, kind="f32"):
-    """Predicted seconds of one call; kind in {'f32', '16bit', 'x3'}.
+    """Predicted seconds of one fused call; kind in {'f32', '16bit', 'x3'}.
     Returns (total_seconds, [per-launch dicts])."""
     dt = {"f32": B.STRASSEN_F32, "16bit": B.STRASSEN_BF16, "x3": B.STRASSEN_F32}[kind]
     mode = B.STRASSEN_MODE_BF16X3 if kind == "x3" else B.STRASSEN_MODE_PLAIN
@@ -102,55 +193,35 @@ def predict(m, n, k, levels, kind="f32"):
     if rc != 0:
         raise ValueError("plan_info failed (%d)" % rc)
     sm, sn, sk = info.sub_m, info.sub_n, info.sub_k
-    b_in = 2 if kind == "16bit" else 4
-    b_lds = 4 if kind == "f32" else 2
-    planes = 2 if kind == "x3" else 1
-    mfma_mult = 3 if kind == "x3" else 1
-    rate_kind = "f32" if kind == "f32" else "16bit"
     launches = []
-    total = 0.0
     for wa, wb, wc, batch in _batches(levels):
         large = _use_large(sm, sn, sk, batch, kind == "f32")
-        mt, nt, kt, waves, slots_per_cu = TILES[(kind, large)]
-        if kind == "f32" and large and wa + wb > 4 and (wa, wb, wc) not in ((4, 1, 4), (4, 2, 2)):
-            kt = 16
-        if kind == "16bit" and large and (wa + wb > 4 or (wa, wb) == (1, 2)):
-            kt = 32
-        if kind == "x3" and large and wa + wb == 2:
-            kt = 32
-        tiles = math.ceil(sm / mt) * math.ceil(sn / nt) * batch
-        ktiles = math.ceil(sk / kt)
-        wm, wn = (mt // 2, nt // (waves // 2))
-        flops = 2.0 * mt * nt * kt * ktiles * tiles * mfma_mult
-        lds_w = (mt + nt) * kt * b_lds * planes * ktiles * tiles
-        lds_r = waves * (wm + wn) * kt * b_lds * planes * ktiles * tiles
-        l2 = (wa * mt + wb * nt) * kt * b_in * ktiles * tiles
+        launches.append(launch(kind, large, wa, wb, wc, sm, sn, sk, batch))
+    return sum(l["seconds"] for l in launches), launches
 
-        def staging(w):  # VALU lane-ops per element of one operand tile
-            if kind == "f32":
-                return float(w)
-            if kind == "x3":
-                return 2.0 * w + 3.0
-            return 0.125 if w == 1 else 2.0 * w + 0.5
-        valu = (mt * staging(wa) + nt * staging(wb)) * kt * ktiles * tiles
-        hbm = batch * (b_in * (wa * sm * sk + wb * sk * sn) + 8 * wc * sm * sn)
-        clock = CLOCK_HZ if kind == "f32" else CLOCK_16BIT_HZ
-        t = {
-            "flop": flops / (CUS * MFMA_FLOP_PER_CLK_CU[rate_kind] * clock),
-            "valu": valu / (CUS * VALU_OPS_PER_CLK_CU * clock),
-            "lds": (lds_w / LDS_WRITE_B_PER_CLK_CU + lds_r / LDS_READ_B_PER_CLK_CU) / (CUS * clock),
-            "l2": l2 / (CUS * L2_B_PER_CLK_CU * clock),
-            "hbm": hbm / HBM_B_PER_S,
-        }
-        slots = CUS * slots_per_cu
-        quant = math.ceil(tiles / slots) / (tiles / slots)
-        limits = {"compute": t["flop"] + t["valu"], "lds": t["lds"], "l2": t["l2"], "hbm": t["hbm"]}
-        bound = max(limits, key=limits.get)
-        secs = limits[bound] * quant + LAUNCH_S
-        if bound == "compute":
-            bound = "flop" if t["flop"] >= t["valu"] else "valu"
-        total += secs
-        launches.append({"variant": (wa, wb, wc), "batch": batch, "tile": (mt, nt, kt),
-                         "workgroups": tiles, "bound": bound, "seconds": secs,
-                         "quantisation": quant, **{"t_" + r: v for r, v in t.items()}})
-    return total, launches
+
+def parse_kernel(name):
+    """(kind, large, (W_A, W_B, W_C) or None, chains or 0) from a launch
+    record's kernel name; kind None for the sum-forming kernels."""
+    if name.startswith("form_sums"):
+        return None, False, None, 0
+    kind = "f32" if name.startswith("strassen_f32") else "x3" if "bf16x3" in name else "16bit"
+    large = "256x256" in name
+    args = name[name.rindex("<") + 1:name.rindex(">")].split(",")
+    if args[0] == "chained":
+        return kind, large, None, int(args[1])
+    return kind, large, tuple(int(v) for v in args[:3]), 0
+
+
+def predict_record(kernel, batch, workgroups, sm, sn, sk, kind_hint=None):
+    """Predicted seconds of one recorded launch (kernel name, batch,
+    workgroups as the library records them) on sub-blocks sm x sk x sn.
+    Sum-forming launches: one operand's four quadrants into five sums of
+    sm x sk (kind_hint gives their element type)."""
+    kind, large, variant, chains = parse_kernel(kernel)
+    if kind is None:
+        fk = "16bit" if "16-bit" in kernel else "x3"
+        return form(kind_hint or fk, sm, sk, 4, 5)
+    if chains:
+        return launch(kind, large, 1, 1, 2, sm, sn, sk, chains, products_per_workgroup=2)["seconds"]
+    return launch(kind, large, *variant, sm, sn, sk, batch)["seconds"]

@@ -1,11 +1,15 @@
-"""The performance model (Analysis section, T = max of the resource times per
-launch, with the staging VALU work added to the MFMA time, plus wave
-quantisation and launch overhead) against facts it must reproduce: the flop
-term is the executed MFMA work of the plan, launches are the plan's race-free
-batches, small problems lose to quantisation, one level pays for fp32 but not
-for 16-bit operands, and the 16-bit two-level path leaves the MFMA bound.
-Host only: plan queries need no GPU."""
+"""The performance model (Analysis section, T = max of the resource times,
+per round of workgroups, with the staging VALU work added to the MFMA time,
+the epilogue and a fixed cost per round added, plus launch overhead) against
+facts it must reproduce: the flop term is the executed MFMA work of the plan,
+launches are the plan's race-free batches, small problems lose to partial
+rounds, one level pays for fp32 but not for 16-bit operands, the 16-bit
+two-level path leaves the MFMA bound, and the measured launch and call times
+of squares 1024-16384 (a committed table of MI355X measurements) are
+predicted within the stated errors.  Host only: plan queries need no GPU."""
 import math
+import os
+import re
 
 import pytest
 
@@ -37,52 +41,57 @@ def test_flop_term_is_executed_mfma_work(levels):
 
 def test_plain_gemm_time_is_flops_over_peak_plus_staging():
     """Full tiles: flops over the MFMA peak, plus one VALU op per staged
-    element (the sign multiply), 512 elements per 256x256 tile and k step."""
+    element (the sign multiply), 512 elements per 256x256 tile and k step,
+    plus per round of 256 workgroups the epilogue (a read and a write of
+    each C element) and the fixed round cost."""
     n = 16384
     t, (l,) = model.predict(n, n, n, 0)
     ideal = 2.0 * n ** 3 / (model.CUS * model.MFMA_FLOP_PER_CLK_CU["f32"] * model.CLOCK_HZ)
     staging = (256 + 256) * n * (n // 256) ** 2 / (model.CUS * model.VALU_OPS_PER_CLK_CU * model.CLOCK_HZ)
-    assert l["quantisation"] == 1.0
+    rounds = (n // 256) ** 2 // model.CUS
+    epilogue = rounds * 8.0 * 256 * 256 / model.R_C_B_PER_S_CU
+    assert l["rounds"] == rounds == 16
     assert math.isclose(l["t_flop"], ideal, rel_tol=1e-12)
     assert math.isclose(l["t_valu"], staging, rel_tol=1e-12)
-    assert math.isclose(t, ideal + staging + model.LAUNCH_S, rel_tol=1e-12)
+    assert math.isclose(l["t_epilogue"], epilogue, rel_tol=1e-12)
+    assert math.isclose(t, ideal + staging + epilogue + rounds * model.ROUND_S + model.LAUNCH_S,
+                        rel_tol=1e-12)
 
 
 def test_strassen_pays_at_large_sizes_only():
     """fp32: one level predicted faster than plain at 16384, slower at 1024
-    (fewer, emptier launches: wave quantisation and launch overhead)."""
+    (fewer, emptier launches: partial rounds and launch overhead)."""
     big0, _ = model.predict(16384, 16384, 16384, 0)
     big1, _ = model.predict(16384, 16384, 16384, 1)
     small0, _ = model.predict(1024, 1024, 1024, 0)
     small1, ls = model.predict(1024, 1024, 1024, 1)
     assert big1 < big0
     assert small1 > small0
-    assert any(l["quantisation"] > 1.0 for l in ls)
+    assert all(l["workgroups"] < model.CUS for l in ls)
 
 
 def test_16bit_two_level_leaves_the_mfma_bound():
-    """At 16384 the 16-bit two-level launches are bound by their four-term
-    operand sums (VALU), HBM or L2->CU operand traffic, not by the MFMAs,
-    while fp32 stays MFMA bound at every level."""
-    _, ls = model.predict(16384, 16384, 16384, 2, "16bit")
-    assert all(l["bound"] in ("valu", "hbm", "l2") for l in ls)
+    """At 16384 the 16-bit launches are bound by operand fetch (the bytes a
+    CU keeps in flight), not by the MFMAs, while fp32 stays MFMA bound at
+    levels 0 and 1."""
     for L in (0, 1, 2):
+        _, ls = model.predict(16384, 16384, 16384, L, "16bit")
+        assert all(l["bound"] == "fetch" for l in ls)
+    for L in (0, 1):
         _, lf = model.predict(16384, 16384, 16384, L, "f32")
         assert all(l["bound"] == "flop" for l in lf)
-    _, l0 = model.predict(16384, 16384, 16384, 0, "16bit")
-    assert l0[0]["bound"] in ("flop", "lds")
 
 
 def test_16bit_one_level_costs_more_than_it_saves():
-    """16-bit MFMAs are so fast that forming two-term operand sums (a convert
-    and an FMA per element) costs more than the eighth of the flops one level
-    saves: plain is predicted faster at 16384, as measured (8.4 ms plain, 12.2
-    ms one level, bf16)."""
+    """16-bit MFMAs are so fast that the operand bytes of two-term sums cost
+    more than the eighth of the flops one level saves: plain is predicted
+    faster at 16384, as measured (7.9 ms plain, 11.6 ms one level fused,
+    bf16); each launch's operand fetch outlasts its MFMA work."""
     n = 16384
     t0, _ = model.predict(n, n, n, 0, "16bit")
     t1, ls = model.predict(n, n, n, 1, "16bit")
     assert t1 > t0
-    assert any(l["t_valu"] > 0.5 * l["t_flop"] for l in ls)
+    assert all(l["t_fetch"] > 1.5 * l["t_flop"] for l in ls)
     f0, _ = model.predict(n, n, n, 0, "f32")
     f1, _ = model.predict(n, n, n, 1, "f32")
     assert f1 < f0
@@ -124,3 +133,95 @@ def test_tile_choice_measured_cases(m, levels, tile):
     """Shapes where the faster tile was measured on MI355X (fp32): full 256x256
     waves keep 256x256; 4.5-wave or 2.25-wave launches take 128x128."""
     assert sg.plan_info(m, m, m, levels).tile_m == tile
+
+
+# ---- measured launch and call times (bench.py --launch-table on MI355X) ----
+PROFILE = os.path.join(os.path.dirname(__file__), "..", "profiles", "strassen_launch_times_squares.md")
+KIND = {"fp32": "f32", "bf16": "16bit", "bf16x3": "x3"}
+
+
+def _table(header):
+    rows, cols, on = [], None, False
+    for ln in open(PROFILE):
+        if ln.startswith("## "):
+            on = ln.strip() == "## " + header
+            continue
+        if on and ln.startswith("| ") and not ln.startswith("|---"):
+            cells = [c.strip() for c in ln.strip().strip("|").split("|")]
+            if cols is None:
+                cols = cells
+            else:
+                rows.append(dict(zip(cols, cells)))
+    return rows
+
+
+def _launch_prediction(r):
+    kind, N, L = KIND[r["kind"]], int(r["N"]), int(r["L"])
+    s = N >> (L if r["schedule"] == "fused" else 1)
+    tok = r["kernel"]
+    if tok == "form":
+        return model.form(kind if kind != "f32" else "x3", s, s, 4, 5)
+    m = re.match(r"(\d+) chained (\d+)$", tok)
+    if m:
+        return model.launch(kind, m.group(1) == "256", 1, 1, 2, s, s, s, int(m.group(2)),
+                            products_per_workgroup=2)["seconds"]
+    m = re.match(r"(\d+) \((\d),(\d),(\d)\)$", tok)
+    wa, wb, wc = (int(v) for v in m.group(2, 3, 4))
+    return model.launch(kind, m.group(1) == "256", wa, wb, wc, s, s, s, int(r["batch"]))["seconds"]
+
+
+def test_measured_launches_are_predicted():
+    """Every launch of at least 0.05 ms (the side-stream form excepted, whose
+    event time includes the batch it overlaps): 16-bit and compensated
+    product launches within 27 % and at least 95 % of them within 25 %;
+    fp32 launches at least 95 % within 25 %; the formed schedule's
+    sum-forming launches within 35 %."""
+    rows = _table("Launches")
+    assert len(rows) > 250
+    groups = {"16bit": [], "f32": [], "form": []}
+    for r in rows:
+        if r["note"] == "side":
+            continue
+        pred = _launch_prediction(r)
+        err = pred / (float(r["measured ms"]) * 1e-3) - 1.0
+        if r["kernel"] == "form":
+            groups["form"].append(err)
+            continue
+        groups["f32" if r["kind"] == "fp32" else "16bit"].append(err)
+    e16 = [abs(e) for e in groups["16bit"]]
+    assert len(e16) > 140 and max(e16) <= 0.27
+    assert sum(e <= 0.25 for e in e16) >= 0.95 * len(e16)
+    e32 = [abs(e) for e in groups["f32"]]
+    assert len(e32) > 80 and sum(e <= 0.25 for e in e32) >= 0.95 * len(e32)
+    assert groups["form"] and max(abs(e) for e in groups["form"]) <= 0.35
+
+
+def test_measured_launch_workgroups_match_model():
+    """The workgroup count the model derives from the shape (tiles per
+    product times products, or times chains) equals the recorded one."""
+    for r in _table("Launches"):
+        if r["kernel"] == "form":
+            continue
+        N, L = int(r["N"]), int(r["L"])
+        s = N >> (L if r["schedule"] == "fused" else 1)
+        m = re.match(r"(\d+) ", r["kernel"])
+        t = int(m.group(1))
+        per = math.ceil(s / t) ** 2
+        chains = re.match(r"\d+ chained (\d+)$", r["kernel"])
+        assert int(r["wg"]) == per * (int(chains.group(1)) if chains else int(r["batch"]))
+
+
+def test_measured_calls_are_predicted_at_4096_and_above():
+    """Whole fused calls at m = n = k >= 4096, every level and kind: within
+    20 % (the smaller squares are dominated by per-launch latencies the
+    model does not resolve, and are reported, not gated)."""
+    rows = _table("Calls")
+    assert len(rows) == 45
+    checked = 0
+    for r in rows:
+        N = int(r["N"])
+        t, _ = model.predict(N, N, N, int(r["levels"]), KIND[r["kind"]])
+        if N >= 4096:
+            assert abs(t / (float(r["measured ms"]) * 1e-3) - 1.0) <= 0.20, r
+            checked += 1
+    assert checked == 27
