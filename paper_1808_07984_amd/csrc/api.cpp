@@ -881,12 +881,16 @@ int run_formed(const Call &c, void *ws, bool side = true) {
     // Chains (16-bit kernels): a batch of two-output products each of which
     // shares an output block with a distinct single-output product becomes
     // one chained launch, and those single-output products leave their own
-    // batches.  At one level: {M2, M3} with M5 (C3) and M6 (C0).
+    // batches.  Of the batches that qualify, the one with the most chains,
+    // and among those one that reads B's sums anyway (the batches that read
+    // B as stored run beside B's form); at one level: {M2, M3} with M5 (C3)
+    // and M6 (C0).
     std::vector<int> head_of(plan.products.size(), -1);  // single-output product -> its chain head
     std::vector<int> carry_of(plan.products.size(), 0);  // chain head -> 1 + carried output
     int chained_batch = -1;
+    int best_score = 0;
     if (fam.m16) {
-        for (size_t bi = 0; bi < plan.batches.size() && chained_batch < 0; ++bi) {
+        for (size_t bi = 0; bi < plan.batches.size(); ++bi) {
             const strassen::Batch &bt = plan.batches[bi];
             if (bt.wc != 2 || 2 * bt.products.size() > (size_t)strassen::kMaxBatchArgs ||
                 !use_large(sm, sn, sk, (int)bt.products.size(), false))
@@ -910,6 +914,11 @@ int run_formed(const Call &c, void *ws, bool side = true) {
                 all = all && found;
             }
             if (!all) continue;
+            bool reads_b_sums = false;
+            for (int x : bt.products) reads_b_sums = reads_b_sums || g.b_of[x] >= 0;
+            const int score = 2 * (int)bt.products.size() + (reads_b_sums ? 1 : 0);
+            if (score <= best_score) continue;
+            best_score = score;
             chained_batch = (int)bi;
             head_of = pick;
             carry_of = carry;

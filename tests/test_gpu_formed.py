@@ -93,7 +93,15 @@ def test_formed_chained_16bit(fam, kind):
     m, n, k = 8192, 4096, 1024
     prob = make_problem(m, n, k, kind=kind, dtype=dtype, c_kind=kind, int_range=(-1, 1))
     d1, d2 = to_device(prob), to_device(prob)
+    assert sg.strassen_profile_start() == 0
     got = _formed(d1, 1.0, 1.0, mode)
+    rc, recs = sg.strassen_profile_stop()
+    names = [r.kernel.decode() for r in recs[:rc]]
+    # two sum-forming launches, M1 and M4 as one batch, M0 alone, and one
+    # chained launch of the two chains M2 -> M5 and M3 -> M6
+    assert sum(nm.startswith("form_sums") for nm in names) == 2
+    assert sum("<chained,2," in nm for nm in names) == 1
+    assert len(names) == 5, names
     if kind == "integers":
         rows, cols = stratified_entries(m, n, 1, 7)
         want = oracle.gemm_entries(prob["A"], prob["B"], prob["C"], rows, cols, 1.0, 1.0)
