@@ -315,12 +315,13 @@ def precision_section(sizes, steps, dev, stream, log):
                 scale = N * float(Ah.float().abs().max()) * float(Bh.float().abs().max())
                 A, B = Ah.to(dev), Bh.to(dev)
                 C = torch.zeros(N, N, device=dev)
-                ws = torch.empty(sg.api.formed_workspace_bytes(N, N, N, tdt, mode), dtype=torch.uint8,
-                                 device=dev)
-                for L in (0, 1, "1_formed", 2):
-                    if L == "1_formed":
-                        call = (lambda: sg.gemm_formed(A, B, C, 1.0, 0.0, mode=mode, workspace=ws))
-                        lv = 1
+                ws = torch.empty(max(sg.api.formed_workspace_bytes(N, N, N, tdt, mode, lv_) for lv_ in (1, 2)),
+                                 dtype=torch.uint8, device=dev)
+                for L in (0, 1, "1_formed", 2, "2_formed"):
+                    if L in ("1_formed", "2_formed"):
+                        lv = int(L[0])
+                        call = (lambda lv=lv: sg.gemm_formed(A, B, C, 1.0, 0.0, mode=mode, workspace=ws,
+                                                             levels=lv))
                     else:
                         call = (lambda L=L: sg.gemm(A, B, C, 1.0, 0.0, levels=L, mode=mode))
                         lv = L
@@ -381,13 +382,14 @@ def compensated_section(sizes, steps, rounds, dev, stream, log):
         A = inputs.normal(N, N, inputs.SEED_A).to(dev)
         B = inputs.normal(N, N, inputs.SEED_B).to(dev)
         C = torch.zeros(N, N, device=dev)
-        ws = torch.empty(sg.api.formed_workspace_bytes(N, N, N, torch.float32, "bf16x3"),
+        ws = torch.empty(max(sg.api.formed_workspace_bytes(N, N, N, torch.float32, "bf16x3", lv) for lv in (1, 2)),
                          dtype=torch.uint8, device=dev)
         variants = {
             "L0": lambda: sg.gemm(A, B, C, 1.0, 0.0, levels=0, mode="bf16x3"),
             "L1_fused": lambda: sg.gemm(A, B, C, 1.0, 0.0, levels=1, mode="bf16x3"),
             "L1_formed": lambda: sg.gemm_formed(A, B, C, 1.0, 0.0, mode="bf16x3", workspace=ws),
             "L2_fused": lambda: sg.gemm(A, B, C, 1.0, 0.0, levels=2, mode="bf16x3"),
+            "L2_formed": lambda: sg.gemm_formed(A, B, C, 1.0, 0.0, mode="bf16x3", workspace=ws, levels=2),
         }
         # correctness first: formed == fused, sampled errors vs fp64
         rng = np.random.default_rng(N + 1)
@@ -395,7 +397,7 @@ def compensated_section(sizes, steps, rounds, dev, stream, log):
         want, _ = sampled_reference(A, B, None, rows, cols, 1.0, 0.0)
         scale = N * float(A.abs().max()) * float(B.abs().max())
         errs = {}
-        ref1 = None
+        ref1 = ref2 = None
         for name, fn in variants.items():
             fn()
             torch.cuda.synchronize()
@@ -404,6 +406,10 @@ def compensated_section(sizes, steps, rounds, dev, stream, log):
                           "e_norm_2m23": round(err / (2.0 ** -23 * scale), 4)}
             if name == "L1_fused":
                 ref1 = C.clone()
+            if name == "L2_fused":
+                ref2 = C.clone()
+            if name == "L2_formed" and not torch.equal(C, ref2):
+                raise SystemExit("formed two-level result differs from the fused one at N=%d" % N)
             if name == "L1_formed":
                 # C1 and C2 equal the fused call bit for bit; C0 and C3 take the
                 # chained products (added together with their partners)
@@ -411,7 +417,7 @@ def compensated_section(sizes, steps, rounds, dev, stream, log):
                 if not (torch.equal(C[:h, h:], ref1[:h, h:]) and torch.equal(C[h:, :h], ref1[h:, :h])
                         and errs[name]["e_norm_2m16"] <= 4.0):
                     raise SystemExit("formed one-level result check failed at N=%d" % N)
-        del ref1
+        del ref1, ref2
         times = {name: [] for name in variants}
         for _ in range(rounds):
             for name, fn in variants.items():
@@ -432,12 +438,14 @@ def compensated_section(sizes, steps, rounds, dev, stream, log):
         row["L1_formed"]["workspace_bytes"] = int(ws.numel())
         row["L1_formed_vs_L0"] = round(row["L0"]["ms_per_step"] / row["L1_formed"]["ms_per_step"], 4)
         row["L1_fused_vs_L0"] = round(row["L0"]["ms_per_step"] / row["L1_fused"]["ms_per_step"], 4)
+        row["L2_formed_vs_L0"] = round(row["L0"]["ms_per_step"] / row["L2_formed"]["ms_per_step"], 4)
         out[str(N)] = row
         log("bf16x3 N=%d (median of %d rounds): L0 %.3f  L1 fused %.3f  L1 formed %.3f (forms %.3f)  "
-            "L2 %.3f ms;  formed speedup over plain %.3fx, fused %.3fx"
+            "L2 fused %.3f  L2 formed %.3f ms;  formed speedup over plain %.3fx (L1) %.3fx (L2), fused %.3fx"
             % (N, rounds, row["L0"]["ms_per_step"], row["L1_fused"]["ms_per_step"],
                row["L1_formed"]["ms_per_step"], forms, row["L2_fused"]["ms_per_step"],
-               row["L1_formed_vs_L0"], row["L1_fused_vs_L0"]))
+               row["L2_formed"]["ms_per_step"], row["L1_formed_vs_L0"], row["L2_formed_vs_L0"],
+               row["L1_fused_vs_L0"]))
         del A, B, C, ws
         torch.cuda.empty_cache()
     return out
@@ -604,13 +612,14 @@ def launch_table(path, dev, stream, log, sizes=(1024, 2048, 4096, 8192, 16384), 
         operands = {"f32": (Af, Bf, "plain"), "bf16": (Af.bfloat16(), Bf.bfloat16(), "plain"),
                     "x3": (Af, Bf, "bf16x3")}
         cases = [(kind, L, "fused") for kind in ("f32", "bf16", "x3") for L in (0, 1, 2)]
-        cases += [("bf16", 1, "formed"), ("x3", 1, "formed")]
+        cases += [("bf16", 1, "formed"), ("x3", 1, "formed"), ("f32", 2, "formed"), ("bf16", 2, "formed"),
+                  ("x3", 2, "formed")]
         for kind, L, sched in cases:
             A, B, mode = operands[kind]
             if sched == "formed":
-                ws = torch.empty(sg.api.formed_workspace_bytes(N, N, N, A.dtype, mode),
+                ws = torch.empty(sg.api.formed_workspace_bytes(N, N, N, A.dtype, mode, L),
                                  dtype=torch.uint8, device=dev)
-                fn = lambda: sg.gemm_formed(A, B, C, 1.0, 0.0, mode=mode, workspace=ws)
+                fn = lambda: sg.gemm_formed(A, B, C, 1.0, 0.0, mode=mode, workspace=ws, levels=L)
             else:
                 fn = lambda: sg.gemm(A, B, C, 1.0, 0.0, levels=L, mode=mode)
             call_ms = [time_calls(fn, 1, 1 if r == 0 else 0, stream) for r in range(reps)]
@@ -737,6 +746,30 @@ def main():
                               "workspace_bytes": int(ws.numel())}
     log("L2 hybrid: %.3f ms/step  effective %.1f TFLOP/s  (sampled e_norm %.4f)"
         % (ms, per_level["L2_hybrid"]["effective_tflops"], en))
+    del ws
+
+    # Formed two-level schedule (every multi-term operand sum formed into
+    # caller workspace first, then 49 single-term products): bit-identical to
+    # the fused two-level call
+    ws = torch.empty(sg.api.formed_workspace_bytes(m, n, k, torch.float32, "plain", 2), dtype=torch.uint8,
+                     device=dev)
+    C.copy_(C0)
+    sg.gemm(A, B, C, 1.0, 1.0, levels=2)
+    ref2 = C.clone()
+    C.copy_(C0)
+    sg.gemm_formed(A, B, C, 1.0, 1.0, workspace=ws, levels=2)
+    torch.cuda.synchronize()
+    if not torch.equal(C, ref2):
+        raise SystemExit("formed two-level result differs from the fused one")
+    del ref2
+    ms = time_calls(lambda: sg.gemm_formed(A, B, C, 1.0, 1.0, workspace=ws, levels=2), args.steps,
+                    args.warmup, stream)
+    per_level["L2_formed"] = {"ms_per_step": round(ms, 4),
+                              "effective_tflops": round(2.0 * m * n * k / (ms * 1e-3) / 1e12, 2),
+                              "executed_tflops": round(info2.executed_flops / (ms * 1e-3) / 1e12, 2),
+                              "workspace_bytes": int(ws.numel())}
+    log("L2 formed: %.3f ms/step  effective %.1f TFLOP/s  (equal to the fused two-level result)"
+        % (ms, per_level["L2_formed"]["effective_tflops"]))
     del ws
 
     # Dominant kernel of the headline level: the instantiation with the most

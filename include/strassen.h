@@ -173,6 +173,36 @@ int strassen_gemm_formed(int64_t m, int64_t n, int64_t k,
 int64_t strassen_formed_workspace_size(int64_t m, int64_t n, int64_t k,
                                        strassen_dtype_t dtype, strassen_mode_t mode);
 
+/* strassen_gemm_formed at one or two levels (levels = 1 or 2; eq.
+ * "gpu_allops" applied twice, the Two-Level Strassen's Algorithm section's
+ * 49 products).  At two levels every multi-term operand of the 49 products
+ * (25 four-term and 20 two-term sums of A, the same of B, on the 4 x 4 block
+ * grid) is formed once into workspace, one launch per level-1 operand
+ * reading its at most eight blocks once, with the fused kernels' arithmetic
+ * (terms added in order, one fused multiply-add each, in fp32 from the
+ * stored values, 16-bit data rounded once); then the 49 products run the
+ * single-term kernel in the race-free batches and the launch order of
+ * strassen_gemm_ex at levels = 2, so the result equals that call's bit for
+ * bit.  At one level the same as strassen_gemm_formed.  Arguments as
+ * strassen_gemm_formed with levels inserted: m=1 n=2 k=3 A=4 lda=5 a_type=6
+ * B=7 ldb=8 b_type=9 C=10 ldc=11 alpha=12 beta=13 levels=14 mode=15
+ * workspace=16 workspace_bytes=17 hip_stream=18. */
+int strassen_gemm_formed_ex(int64_t m, int64_t n, int64_t k,
+                            const void *A, int64_t lda, strassen_dtype_t a_type,
+                            const void *B, int64_t ldb, strassen_dtype_t b_type,
+                            float *C, int64_t ldc,
+                            float alpha, float beta, int levels, strassen_mode_t mode,
+                            void *workspace, int64_t workspace_bytes, void *hip_stream);
+
+/* Workspace bytes strassen_gemm_formed_ex needs: at one level as
+ * strassen_formed_workspace_size; at two levels e * 45 (sm sk + sk sn) with
+ * the two-level block extents sm = ceil(m/4), sk = ceil(k/4), sn = ceil(n/4)
+ * (sk, sn rounded up as above), about 2.8 (mk + kn) e bytes.  Returns the
+ * size, or a negative argument index (m=1 n=2 k=3 levels=4 dtype=5 mode=6).
+ * Pure host computation. */
+int64_t strassen_formed_workspace_size_ex(int64_t m, int64_t n, int64_t k, int levels,
+                                          strassen_dtype_t dtype, strassen_mode_t mode);
+
 /* strassen_gemm_formed without a workspace argument and without any
  * allocation, for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the

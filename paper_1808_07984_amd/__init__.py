@@ -11,7 +11,7 @@ and the formed one-level schedules take caller workspace).
     import paper_1808_07984_amd as sg
     sg.gemm(A, B, C, alpha=1.0, beta=1.0, levels=1)      # torch tensors
     sg.strassen_gemm(m, n, k, pA, lda, pB, ldb, pC, ldc, alpha, beta, levels)
-    sg.gemm_formed(A, B, C, mode="bf16x3")   # one level, sums formed first
+    sg.gemm_formed(A, B, C, mode="bf16x3")   # one level, sums formed first (levels=2: two)
 
 The C ABI (include/strassen.h) lives in _build/libstrassen.so; this package
 binds it with ctypes.  Importing fails if the library is not built.
@@ -36,10 +36,12 @@ from ._binding import (  # noqa: F401
     strassen_gemm,
     strassen_gemm_ex,
     strassen_gemm_formed,
+    strassen_gemm_formed_ex,
     strassen_gemm_formed_noalloc,
     STRASSEN_NOALLOC_SCRATCH_BYTES,
     STRASSEN_ERROR_SCRATCH_LIMIT,
     strassen_formed_workspace_size,
+    strassen_formed_workspace_size_ex,
     strassen_gemm_hybrid,
     strassen_hybrid_workspace_size,
     strassen_plan_info,

@@ -74,6 +74,9 @@ SIGNATURES = {
     "strassen_gemm_formed": (_int, [_i64, _i64, _i64, _vp, _i64, _int, _vp, _i64, _int, _vp, _i64,
                                     _f32, _f32, _int, _vp, _i64, _vp]),
     "strassen_formed_workspace_size": (_i64, [_i64, _i64, _i64, _int, _int]),
+    "strassen_gemm_formed_ex": (_int, [_i64, _i64, _i64, _vp, _i64, _int, _vp, _i64, _int, _vp, _i64,
+                                       _f32, _f32, _int, _int, _vp, _i64, _vp]),
+    "strassen_formed_workspace_size_ex": (_i64, [_i64, _i64, _i64, _int, _int, _int]),
     "strassen_gemm_formed_noalloc": (_int, [_i64, _i64, _i64, _vp, _i64, _int, _vp, _i64, _int, _vp,
                                             _i64, _f32, _f32, _int, _vp]),
     "strassen_set_stream": (_int, [_vp]),
@@ -200,6 +203,16 @@ def strassen_gemm_formed_noalloc(m, n, k, A, lda, a_type, B, ldb, b_type, C, ldc
 
 def strassen_formed_workspace_size(m, n, k, dtype=STRASSEN_F32, mode=STRASSEN_MODE_PLAIN):
     return lib.strassen_formed_workspace_size(m, n, k, dtype, mode)
+
+
+def strassen_gemm_formed_ex(m, n, k, A, lda, a_type, B, ldb, b_type, C, ldc, alpha, beta, levels, mode,
+                            workspace, workspace_bytes, hip_stream):
+    return lib.strassen_gemm_formed_ex(m, n, k, A, lda, a_type, B, ldb, b_type, C, ldc, alpha, beta,
+                                       levels, mode, workspace, workspace_bytes, hip_stream)
+
+
+def strassen_formed_workspace_size_ex(m, n, k, levels=1, dtype=STRASSEN_F32, mode=STRASSEN_MODE_PLAIN):
+    return lib.strassen_formed_workspace_size_ex(m, n, k, levels, dtype, mode)
 
 
 def strassen_set_stream(hip_stream):

@@ -92,21 +92,22 @@ def gemm_hybrid(A, B_, C, alpha=1.0, beta=1.0, workspace=None, stream=None):
     return C
 
 
-def formed_workspace_bytes(m, n, k, dtype=torch.float32, mode="plain"):
-    """Bytes of workspace gemm_formed needs for this shape, dtype and mode."""
-    need = B.strassen_formed_workspace_size(m, n, k, _DTYPES[dtype], _MODES[mode])
+def formed_workspace_bytes(m, n, k, dtype=torch.float32, mode="plain", levels=1):
+    """Bytes of workspace gemm_formed needs for this shape, dtype, mode and
+    number of levels."""
+    need = B.strassen_formed_workspace_size_ex(m, n, k, levels, _DTYPES[dtype], _MODES[mode])
     if need < 0:
-        raise B.StrassenError(int(need), "strassen_formed_workspace_size")
+        raise B.StrassenError(int(need), "strassen_formed_workspace_size_ex")
     return need
 
 
-def gemm_formed(A, B_, C, alpha=1.0, beta=1.0, mode="plain", workspace=None, stream=None):
-    """One-level Strassen with the two-term operand sums formed first into
-    workspace: C := alpha * A @ B + beta * C in place.  Equal to
-    gemm(..., levels=1) bit for bit, except that on the 16-bit matrix cores
-    with 256x256 tiles the products M5 and M6 are accumulated after M2 and M3
-    and added into C3 and C0 with them, so those two blocks can differ in the
-    last bits.  A, B: fp32, bf16 or fp16 GPU tensors of one dtype,
+def gemm_formed(A, B_, C, alpha=1.0, beta=1.0, mode="plain", workspace=None, stream=None, levels=1):
+    """One- or two-level Strassen with the multi-term operand sums formed
+    first into workspace: C := alpha * A @ B + beta * C in place.  Equal to
+    gemm(..., levels=levels) bit for bit, except that at one level on the
+    16-bit matrix cores with 256x256 tiles the products M5 and M6 are
+    accumulated after M2 and M3 and added into C3 and C0 with them, so those
+    two blocks can differ in the last bits.  A, B: fp32, bf16 or fp16 GPU tensors of one dtype,
     as stored (no transposes); C fp32.  `workspace` is a GPU tensor of at
     least formed_workspace_bytes(...) bytes (allocated by torch here when not
     given: the library itself allocates nothing).  Returns C."""
@@ -122,7 +123,7 @@ def gemm_formed(A, B_, C, alpha=1.0, beta=1.0, mode="plain", workspace=None, str
     kb, n = B_.shape
     if kb != k or tuple(C.shape) != (m, n):
         raise ValueError("shape mismatch: A %s, B %s, C %s" % (tuple(A.shape), tuple(B_.shape), tuple(C.shape)))
-    need = formed_workspace_bytes(m, n, k, A.dtype, mode)
+    need = formed_workspace_bytes(m, n, k, A.dtype, mode, levels)
     if workspace is None:
         workspace = torch.empty(max(need, 16), dtype=torch.uint8, device=C.device)
     wbytes = workspace.numel() * workspace.element_size()
@@ -130,10 +131,10 @@ def gemm_formed(A, B_, C, alpha=1.0, beta=1.0, mode="plain", workspace=None, str
         raise ValueError("workspace smaller than %d bytes" % need)
     with torch.cuda.device(C.device):
         s = stream if stream is not None else torch.cuda.current_stream(C.device)
-        rc = B.strassen_gemm_formed(m, n, k, A.data_ptr(), _ld(A, "A"), _DTYPES[A.dtype],
-                                    B_.data_ptr(), _ld(B_, "B"), _DTYPES[A.dtype],
-                                    C.data_ptr(), _ld(C, "C"), float(alpha), float(beta),
-                                    _MODES[mode], workspace.data_ptr(), wbytes, s.cuda_stream)
+        rc = B.strassen_gemm_formed_ex(m, n, k, A.data_ptr(), _ld(A, "A"), _DTYPES[A.dtype],
+                                       B_.data_ptr(), _ld(B_, "B"), _DTYPES[A.dtype],
+                                       C.data_ptr(), _ld(C, "C"), float(alpha), float(beta), int(levels),
+                                       _MODES[mode], workspace.data_ptr(), wbytes, s.cuda_stream)
     if rc != 0:
-        raise B.StrassenError(rc, "strassen_gemm_formed")
+        raise B.StrassenError(rc, "strassen_gemm_formed_ex")
     return C

@@ -745,11 +745,11 @@ int run_hybrid(const Call &c, float *ws) {
 // ---------------------------------------------------------------------------
 struct FormedSum {
     int nterms;
-    strassen::Term t[2];  // t[0].sign = +1; t[1].sign relative to the first
+    strassen::Term t[strassen::kMaxTerms];  // t[0].sign = +1; the others relative to the first
 };
 
 struct FormedGeom {
-    Plan plan;                            // one-level plan (block extents)
+    Plan plan;                            // one- or two-level plan (block extents)
     std::vector<FormedSum> asums, bsums;  // distinct multi-term operands
     std::vector<int> a_of, b_of;          // per product: its sum, or -1
     size_t es = 4;                        // bytes per workspace element
@@ -770,11 +770,10 @@ int find_or_add(std::vector<FormedSum> &sums, const strassen::Term *t, int n) {
     return (int)sums.size() - 1;
 }
 
-FormedGeom formed_geom(int64_t m, int64_t n, int64_t k, const Family &fam) {
+FormedGeom formed_geom(int64_t m, int64_t n, int64_t k, const Family &fam, int levels) {
     FormedGeom g;
-    g.plan = strassen::make_plan(m, n, k, 1, fam.vec);
+    g.plan = strassen::make_plan(m, n, k, levels, fam.vec);
     for (const strassen::Product &p : g.plan.products) {
-        if (p.na > 2 || p.nb > 2) throw std::bad_alloc();  // one level: at most two terms
         g.a_of.push_back(p.na > 1 ? find_or_add(g.asums, p.a, p.na) : -1);
         g.b_of.push_back(p.nb > 1 ? find_or_add(g.bsums, p.b, p.nb) : -1);
     }
@@ -792,6 +791,8 @@ int form_operand(const std::vector<FormedSum> &sums, strassen::FormElem fe, size
                  int64_t ldx, int64_t xr, int64_t xc, int64_t srows, int64_t scols, char *out,
                  bool vec, hipStream_t s, int launch) {
     if (sums.empty()) return 0;
+    for (const FormedSum &f : sums)
+        if (f.nterms > 2) return (int)hipErrorInvalidValue;  // one level: at most two terms
     strassen::FormSource src[strassen::kFormMaxSources];
     int blocks[strassen::kFormMaxSources];
     int nsrc = 0;
@@ -826,6 +827,65 @@ int form_operand(const std::vector<FormedSum> &sums, strassen::FormElem fe, size
     return 0;
 }
 
+// Two levels: the sums of one operand X on the 4 x 4 block grid (block
+// (R, Cc) at X + R*srows*ldx + Cc*scols, extents clipped to xr x xc), up to
+// four terms each, one launch per group of sums whose terms lie in the same
+// level-1 quadrants (the operands of one level-1 product: at most seven sums
+// over at most eight blocks, read once from memory per launch).  Records:
+// batch = sums, workgroups = distinct blocks read.
+int form_operand_terms(const std::vector<FormedSum> &sums, strassen::FormElem fe, size_t es, const void *X,
+                       int64_t ldx, int64_t xr, int64_t xc, int64_t srows, int64_t scols, int d, char *out,
+                       bool vec, hipStream_t s, int *launch) {
+    std::vector<std::pair<int, std::vector<int>>> groups;  // level-1 quadrant mask -> sums
+    for (size_t i = 0; i < sums.size(); ++i) {
+        int mask = 0;
+        for (int t = 0; t < sums[i].nterms; ++t) {
+            const int R = sums[i].t[t].block / d, Cc = sums[i].t[t].block % d;
+            mask |= 1 << ((R * 2 / d) * 2 + Cc * 2 / d);
+        }
+        size_t gi = 0;
+        while (gi < groups.size() && groups[gi].first != mask) ++gi;
+        if (gi == groups.size()) groups.push_back({mask, {}});
+        groups[gi].second.push_back((int)i);
+    }
+    for (const auto &grp : groups) {
+        for (size_t base = 0; base < grp.second.size(); base += strassen::kFormTermsMaxOutputs) {
+            const size_t nout = std::min(grp.second.size() - base, (size_t)strassen::kFormTermsMaxOutputs);
+            strassen::FormTermsOut o[strassen::kFormTermsMaxOutputs];
+            std::vector<int> blocks;
+            for (size_t j = 0; j < nout; ++j) {
+                const int i = grp.second[base + j];
+                const FormedSum &f = sums[i];
+                o[j].ptr = out + (uint64_t)i * srows * scols * es;
+                o[j].n = f.nterms;
+                o[j].pad = 0;
+                for (int t = 0; t < f.nterms; ++t) {
+                    const int R = f.t[t].block / d, Cc = f.t[t].block % d;
+                    o[j].src[t].ptr = static_cast<const char *>(X) + ((uint64_t)R * srows * ldx + (uint64_t)Cc * scols) * es;
+                    o[j].src[t].rows = (int32_t)strassen::block_extent(xr, srows, R);
+                    o[j].src[t].cols = (int32_t)strassen::block_extent(xc, scols, Cc);
+                    o[j].s[t] = (float)f.t[t].sign;
+                    if (std::find(blocks.begin(), blocks.end(), f.t[t].block) == blocks.end())
+                        blocks.push_back(f.t[t].block);
+                }
+            }
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            bool timed = false;
+            int rc = record_begin(s, &e0, &e1, &timed);
+            if (rc != 0) return rc;
+            const hipError_t err = strassen::launch_form_terms(fe, o, (int)nout, ldx, scols, srows, scols, vec, s);
+            if (err != hipSuccess) return (int)err;
+            if (timed) {
+                rc = record_end(s, e0, e1, fe == strassen::FormElem::kF32 ? "form_terms<f32>" : "form_terms<16-bit>",
+                                *launch, (int)nout, (int)blocks.size(), 0.0);
+                if (rc != 0) return rc;
+            }
+            ++*launch;
+        }
+    }
+    return 0;
+}
+
 // side: B's form may run on a side stream (creating it on first use);
 // false for callers that must not allocate.
 int run_formed(const Call &c, void *ws, bool side = true) {
@@ -833,8 +893,9 @@ int run_formed(const Call &c, void *ws, bool side = true) {
     if (c.k == 0 || c.alpha == 0.f)
         return (int)strassen::launch_scale(c.C, c.ldc, c.m, c.n, c.beta, c.stream);
     const Family fam = family(c.a_type, c.mode);
-    const FormedGeom g = formed_geom(c.m, c.n, c.k, fam);
+    const FormedGeom g = formed_geom(c.m, c.n, c.k, fam, c.levels);
     const Plan &plan = g.plan;
+    const int d = plan.d;
     const int64_t sm = plan.sm, sn = plan.sn, sk = plan.sk;
     const size_t in_es = elem_size(c.a_type);
     char *wa = static_cast<char *>(ws);
@@ -854,12 +915,12 @@ int run_formed(const Call &c, void *ws, bool side = true) {
         if (g.a_of[pi] >= 0) {
             int64_t rows = 0, cols = 0;
             for (int t = 0; t < p.na; ++t) {
-                rows = std::max(rows, strassen::block_extent(c.m, sm, p.a[t].block / 2));
-                cols = std::max(cols, strassen::block_extent(c.k, sk, p.a[t].block % 2));
+                rows = std::max(rows, strassen::block_extent(c.m, sm, p.a[t].block / d));
+                cols = std::max(cols, strassen::block_extent(c.k, sk, p.a[t].block % d));
             }
             return term((int64_t)g.a_of[pi] * sm * sk, rows, cols, p.a[0].sign, false);
         }
-        const int R = p.a[0].block / 2, Cc = p.a[0].block % 2;
+        const int R = p.a[0].block / d, Cc = p.a[0].block % d;
         return term(R * sm * c.lda + Cc * sk, strassen::block_extent(c.m, sm, R),
                     strassen::block_extent(c.k, sk, Cc), p.a[0].sign, false);
     };
@@ -868,12 +929,12 @@ int run_formed(const Call &c, void *ws, bool side = true) {
         if (g.b_of[pi] >= 0) {
             int64_t rows = 0, cols = 0;
             for (int t = 0; t < p.nb; ++t) {
-                rows = std::max(rows, strassen::block_extent(c.k, sk, p.b[t].block / 2));
-                cols = std::max(cols, strassen::block_extent(c.n, sn, p.b[t].block % 2));
+                rows = std::max(rows, strassen::block_extent(c.k, sk, p.b[t].block / d));
+                cols = std::max(cols, strassen::block_extent(c.n, sn, p.b[t].block % d));
             }
             return term((int64_t)g.b_of[pi] * sk * sn, rows, cols, p.b[0].sign, false);
         }
-        const int R = p.b[0].block / 2, Cc = p.b[0].block % 2;
+        const int R = p.b[0].block / d, Cc = p.b[0].block % d;
         return term(R * sk * c.ldb + Cc * sn, strassen::block_extent(c.k, sk, R),
                     strassen::block_extent(c.n, sn, Cc), p.b[0].sign, false);
     };
@@ -889,7 +950,7 @@ int run_formed(const Call &c, void *ws, bool side = true) {
     std::vector<int> carry_of(plan.products.size(), 0);  // chain head -> 1 + carried output
     int chained_batch = -1;
     int best_score = 0;
-    if (fam.m16) {
+    if (fam.m16 && plan.levels == 1) {
         for (size_t bi = 0; bi < plan.batches.size(); ++bi) {
             const strassen::Batch &bt = plan.batches[bi];
             if (bt.wc != 2 || 2 * bt.products.size() > (size_t)strassen::kMaxBatchArgs ||
@@ -925,14 +986,14 @@ int run_formed(const Call &c, void *ws, bool side = true) {
         }
     }
     // C blocks written so far (first updates apply beta), in launch order
-    bool touched[4] = {false, false, false, false};
+    bool touched[16] = {false};
     auto first_of = [&](int block) {
         const bool f = !touched[block];
         touched[block] = true;
         return f;
     };
     auto c_term = [&](const strassen::Term &t, bool first) {
-        const int R = t.block / 2, Cc = t.block % 2;
+        const int R = t.block / d, Cc = t.block % d;
         return term(R * sm * c.ldc + Cc * sn, strassen::block_extent(c.m, sm, R),
                     strassen::block_extent(c.n, sn, Cc), t.sign, first);
     };
@@ -1101,10 +1162,18 @@ int run_formed(const Call &c, void *ws, bool side = true) {
             if ((rc = run_batch(bi)) != 0) return rc;
         return 0;
     }
-    rc = form_operand(g.asums, fe, in_es, c.A, c.lda, c.m, c.k, sm, sk, wa, vec_a, c.stream, 0);
-    if (rc != 0) return rc;
-    rc = form_operand(g.bsums, fe, in_es, c.B, c.ldb, c.k, c.n, sk, sn, wb, vec_b, c.stream, 1);
-    if (rc != 0) return rc;
+    if (plan.levels == 1) {
+        rc = form_operand(g.asums, fe, in_es, c.A, c.lda, c.m, c.k, sm, sk, wa, vec_a, c.stream, 0);
+        if (rc != 0) return rc;
+        rc = form_operand(g.bsums, fe, in_es, c.B, c.ldb, c.k, c.n, sk, sn, wb, vec_b, c.stream, 1);
+        if (rc != 0) return rc;
+    } else {
+        launch = 0;
+        rc = form_operand_terms(g.asums, fe, in_es, c.A, c.lda, c.m, c.k, sm, sk, d, wa, vec_a, c.stream, &launch);
+        if (rc != 0) return rc;
+        rc = form_operand_terms(g.bsums, fe, in_es, c.B, c.ldb, c.k, c.n, sk, sn, d, wb, vec_b, c.stream, &launch);
+        if (rc != 0) return rc;
+    }
     for (size_t bi = 0; bi < plan.batches.size(); ++bi)
         if ((rc = run_batch(bi)) != 0) return rc;
     return 0;
@@ -1223,46 +1292,105 @@ int strassen_gemm_hybrid(int64_t m, int64_t n, int64_t k, const float *A, int64_
     }
 }
 
-int64_t strassen_formed_workspace_size(int64_t m, int64_t n, int64_t k, strassen_dtype_t dtype,
-                                       strassen_mode_t mode) {
+}  // extern "C" (reopened below)
+
+namespace {
+
+// Workspace bytes of a formed call, or a negative code: -1 m, -2 n, -3 k,
+// -4 levels, -5 dtype, -6 mode.
+int64_t formed_size(int64_t m, int64_t n, int64_t k, int levels, strassen_dtype_t dtype,
+                    strassen_mode_t mode) {
     if (m < 0 || m >= kMaxDim) return -1;
     if (n < 0 || n >= kMaxDim) return -2;
     if (k < 0 || k >= kMaxDim) return -3;
-    if (!valid_dtype(dtype)) return -4;
-    if (mode != STRASSEN_MODE_PLAIN && mode != STRASSEN_MODE_BF16X3) return -5;
-    if (mode == STRASSEN_MODE_BF16X3 && dtype != STRASSEN_F32) return -5;
+    if (levels != 1 && levels != 2) return -4;
+    if (!valid_dtype(dtype)) return -5;
+    if (mode != STRASSEN_MODE_PLAIN && mode != STRASSEN_MODE_BF16X3) return -6;
+    if (mode == STRASSEN_MODE_BF16X3 && dtype != STRASSEN_F32) return -6;
     try {
-        return formed_geom(m, n, k, family(dtype, mode)).bytes;
+        return formed_geom(m, n, k, family(dtype, mode), levels).bytes;
     } catch (...) {
         return -(int64_t)hipErrorOutOfMemory;
     }
+}
+
+// Maps a strassen_gemm_ex argument index to its strassen_gemm_formed_ex
+// position (the transpose flags cannot be wrong there).
+int to_formed_ex_index(int code) {
+    switch (-code) {
+        case 7: case 11: return -1;  // not reachable
+        case 8: return -7;
+        case 9: return -8;
+        case 10: return -9;
+        case 12: return -10;
+        case 13: return -11;
+        case 14: return -12;
+        case 15: return -13;
+        case 16: return -14;
+        case 17: return -15;
+        default: return code;
+    }
+}
+
+int formed_call(int64_t m, int64_t n, int64_t k, const void *A, int64_t lda, strassen_dtype_t a_type,
+                const void *B, int64_t ldb, strassen_dtype_t b_type, float *C, int64_t ldc, float alpha,
+                float beta, int levels, strassen_mode_t mode, void *workspace, int64_t workspace_bytes,
+                void *hip_stream) {
+    const Call c{m, n, k, A, lda, a_type, 0, B, ldb, b_type, 0, C, ldc,
+                 alpha, beta, levels, mode, (hipStream_t)hip_stream};
+    const int v = validate(c);
+    if (v != 0) return to_formed_ex_index(v);
+    if (levels != 1 && levels != 2) return -14;
+    const bool product = m > 0 && n > 0 && k > 0 && alpha != 0.f;
+    try {
+        if (!product) return run_formed(c, nullptr);
+        const int64_t need = formed_size(m, n, k, levels, a_type, mode);
+        if (need < 0) return (int)(-need);
+        if (workspace == nullptr || (uintptr_t)workspace % 16 != 0) return -16;
+        if (workspace_bytes < need) return -17;
+        const uint64_t wbytes = (uint64_t)need;
+        const size_t es = elem_size(a_type);
+        if (overlap(workspace, wbytes, A, span_bytes(m, k, lda, es)) ||
+            overlap(workspace, wbytes, B, span_bytes(k, n, ldb, es)) ||
+            overlap(workspace, wbytes, C, span_bytes(m, n, ldc, 4)))
+            return -16;
+        return run_formed(c, workspace);
+    } catch (...) {
+        return (int)hipErrorOutOfMemory;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t strassen_formed_workspace_size_ex(int64_t m, int64_t n, int64_t k, int levels, strassen_dtype_t dtype,
+                                          strassen_mode_t mode) {
+    return formed_size(m, n, k, levels, dtype, mode);
+}
+
+int64_t strassen_formed_workspace_size(int64_t m, int64_t n, int64_t k, strassen_dtype_t dtype,
+                                       strassen_mode_t mode) {
+    const int64_t r = formed_size(m, n, k, 1, dtype, mode);
+    return r == -5 ? -4 : r == -6 ? -5 : r;
+}
+
+int strassen_gemm_formed_ex(int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
+                            strassen_dtype_t a_type, const void *B, int64_t ldb, strassen_dtype_t b_type,
+                            float *C, int64_t ldc, float alpha, float beta, int levels, strassen_mode_t mode,
+                            void *workspace, int64_t workspace_bytes, void *hip_stream) {
+    return formed_call(m, n, k, A, lda, a_type, B, ldb, b_type, C, ldc, alpha, beta, levels, mode, workspace,
+                       workspace_bytes, hip_stream);
 }
 
 int strassen_gemm_formed(int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
                          strassen_dtype_t a_type, const void *B, int64_t ldb, strassen_dtype_t b_type,
                          float *C, int64_t ldc, float alpha, float beta, strassen_mode_t mode,
                          void *workspace, int64_t workspace_bytes, void *hip_stream) {
-    const Call c{m, n, k, A, lda, a_type, 0, B, ldb, b_type, 0, C, ldc,
-                 alpha, beta, 1, mode, (hipStream_t)hip_stream};
-    const int v = validate(c);
-    if (v != 0) return to_formed_index(v);
-    const bool product = m > 0 && n > 0 && k > 0 && alpha != 0.f;
-    try {
-        if (!product) return run_formed(c, nullptr);
-        const int64_t need = strassen_formed_workspace_size(m, n, k, a_type, mode);
-        if (need < 0) return (int)(-need);
-        if (workspace == nullptr || (uintptr_t)workspace % 16 != 0) return -15;
-        if (workspace_bytes < need) return -16;
-        const uint64_t wbytes = (uint64_t)need;
-        const size_t es = elem_size(a_type);
-        if (overlap(workspace, wbytes, A, span_bytes(m, k, lda, es)) ||
-            overlap(workspace, wbytes, B, span_bytes(k, n, ldb, es)) ||
-            overlap(workspace, wbytes, C, span_bytes(m, n, ldc, 4)))
-            return -15;
-        return run_formed(c, workspace);
-    } catch (...) {
-        return (int)hipErrorOutOfMemory;
-    }
+    // the _ex positions from levels on are one further
+    const int r = formed_call(m, n, k, A, lda, a_type, B, ldb, b_type, C, ldc, alpha, beta, 1, mode, workspace,
+                              workspace_bytes, hip_stream);
+    return r <= -15 ? r + 1 : r;
 }
 
 static_assert(strassen::kNoAllocScratchBytes == STRASSEN_NOALLOC_SCRATCH_BYTES,
@@ -1279,7 +1407,7 @@ int strassen_gemm_formed_noalloc(int64_t m, int64_t n, int64_t k, const void *A,
     const bool product = m > 0 && n > 0 && k > 0 && alpha != 0.f;
     try {
         if (!product) return run_formed(c, nullptr);
-        const int64_t need = strassen_formed_workspace_size(m, n, k, a_type, mode);
+        const int64_t need = formed_size(m, n, k, 1, a_type, mode);
         if (need < 0) return (int)(-need);
         if (need > strassen::kNoAllocScratchBytes) return STRASSEN_ERROR_SCRATCH_LIMIT;
         void *scratch = nullptr;

@@ -1083,10 +1083,11 @@ hipError_t dispatch(int wa, int wb, int wc, const LaunchArgs &a, int batch, bool
     STRASSEN_CASE(2, 2, 1)
     STRASSEN_CASE(1, 2, 2)
     STRASSEN_CASE(2, 1, 2)
-    // formed one-level schedule (operands as stored): single-term products
-    // with two outputs
+    // formed schedules (operands as stored): single-term products with two
+    // outputs (one level) or four (two levels)
     if constexpr (A_KC && !B_KC) {
         STRASSEN_CASE(1, 1, 2)
+        STRASSEN_CASE(1, 1, 4)
     }
     STRASSEN_CASE(4, 4, 4)
     STRASSEN_CASE(1, 4, 4)

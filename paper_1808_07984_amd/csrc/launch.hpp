@@ -97,6 +97,24 @@ hipError_t launch_form_sums(FormElem elem, const FormSource *src, int nsrc, int6
                             const FormOut *out, int nout, int64_t ld_out, int64_t rows, int64_t cols,
                             bool vec, hipStream_t s);
 
+// Two-level "formed" schedule: out_o = x_0 + sum_{t >= 1} s_t * x_t over up to
+// four terms, each term a block of its own (pointer and rows x cols extent,
+// zero outside it, all sharing ld_src), for up to eight outputs; the terms
+// are added in order with one fused multiply-add each, in fp32 from the
+// stored element type, 16-bit outputs rounded once to nearest even -- the
+// arithmetic of the fused kernels' operand staging.  Layout rules as for
+// launch_form_sums.
+constexpr int kFormTermsMax = 4, kFormTermsMaxOutputs = 8;
+struct FormTermsOut {
+    void *ptr;
+    int32_t n;                           // terms, 1..kFormTermsMax
+    int32_t pad;
+    FormSource src[kFormTermsMax];
+    float s[kFormTermsMax];              // s[0] unused (the first term is added as is)
+};
+hipError_t launch_form_terms(FormElem elem, const FormTermsOut *out, int nout, int64_t ld_src,
+                             int64_t ld_out, int64_t rows, int64_t cols, bool vec, hipStream_t s);
+
 // strassen_gemm_formed_noalloc: the device address of the library's fixed
 // scratch array (kNoAllocScratchBytes, 256-byte aligned) on the device of
 // `stream` (the current device for the null stream), looked up once per

@@ -32,7 +32,7 @@ measured on MI355X:
 
 R_A, R_B, R_C, T_round and the 0.9 factor of the 128 x 128 tile's operand
 rates are fitted to the event times of every launch of squares 1024-16384 at
-levels 0/1/2 (fp32, bf16 and the compensated mode).  They are per-CU rates
+levels 0/1/2 (fp32, bf16 and the compensated mode, fused and formed).  They are per-CU rates
 of latency-bound loads, not bandwidths: the sixteen-bit kernels reach about
 a third of their MFMA peak on the plain product, and their multi-term launches
 are set by how many operand bytes a CU can keep in flight.  The B operand
@@ -42,9 +42,9 @@ each A panel eight ways and each B panel only four ways.  Clocks are the
 measured ones: fp32 under the GEMM (GRBM_GUI_ACTIVE), 16-bit under sustained
 MFMA work on random operands, which is power limited (~1.65 GHz).
 
-Also modelled: the formed one-level schedule's sum kernels (streaming, at a
-measured 5 TB/s) and its chained launches (two products per workgroup, one
-epilogue).
+Also modelled: the formed schedules' sum kernels (streaming, at a measured
+5 TB/s) and the one-level schedule's chained launches (two products per
+workgroup, one epilogue).
 """
 import math
 
@@ -57,11 +57,11 @@ MFMA_FLOP_PER_CLK_CU = {"f32": 256.0, "16bit": 4096.0}
 LDS_WRITE_B_PER_CLK_CU = 128.0
 LDS_READ_B_PER_CLK_CU = 256.0
 VALU_OPS_PER_CLK_CU = 64.0   # 4 SIMDs x 16 lanes
-R_A_B_PER_S_CU = 55e9        # A-operand bytes per second per CU (fitted)
-R_B_B_PER_S_CU = 28e9        # B-operand bytes per second per CU (fitted)
-R_C_B_PER_S_CU = 30e9        # epilogue C bytes per second per CU (fitted)
+R_A_B_PER_S_CU = 60e9        # A-operand bytes per second per CU (fitted)
+R_B_B_PER_S_CU = 31e9        # B-operand bytes per second per CU (fitted)
+R_C_B_PER_S_CU = 24e9        # epilogue C bytes per second per CU (fitted)
 SMALL_TILE_FETCH = 0.9       # 128x128 tile: operand time factor (fitted)
-ROUND_S = 4e-6               # fixed cost per round of workgroups (fitted)
+ROUND_S = 6e-6               # fixed cost per round of workgroups (fitted)
 FORM_B_PER_S = 5.0e12        # sum-forming kernels, bytes read + written (measured)
 HBM_B_PER_S = 8.0e12
 LAUNCH_S = 6e-6
@@ -203,7 +203,7 @@ def predict(m, n, k, levels, kind="f32"):
 def parse_kernel(name):
     """(kind, large, (W_A, W_B, W_C) or None, chains or 0) from a launch
     record's kernel name; kind None for the sum-forming kernels."""
-    if name.startswith("form_sums"):
+    if name.startswith("form_"):
         return None, False, None, 0
     kind = "f32" if name.startswith("strassen_f32") else "x3" if "bf16x3" in name else "16bit"
     large = "256x256" in name
@@ -216,11 +216,14 @@ def parse_kernel(name):
 def predict_record(kernel, batch, workgroups, sm, sn, sk, kind_hint=None):
     """Predicted seconds of one recorded launch (kernel name, batch,
     workgroups as the library records them) on sub-blocks sm x sk x sn.
-    Sum-forming launches: one operand's four quadrants into five sums of
-    sm x sk (kind_hint gives their element type)."""
+    Sum-forming launches: one level, one operand's four quadrants into five
+    sums of sm x sk; two levels (form_terms), `workgroups` distinct blocks
+    into `batch` sums (kind_hint gives their element type)."""
     kind, large, variant, chains = parse_kernel(kernel)
     if kind is None:
         fk = "16bit" if "16-bit" in kernel else "x3"
+        if kernel.startswith("form_terms"):
+            return form(kind_hint or fk, sm, sk, workgroups, batch)
         return form(kind_hint or fk, sm, sk, 4, 5)
     if chains:
         return launch(kind, large, 1, 1, 2, sm, sn, sk, chains, products_per_workgroup=2)["seconds"]

@@ -172,6 +172,51 @@ def test_formed_workspace_size():
     assert f(1, 1, 1, sg.STRASSEN_BF16, sg.STRASSEN_MODE_BF16X3) == -5
 
 
+def test_formed_workspace_size_two_levels():
+    # e * 45 (sm sk + sk sn), two-level extents (ceil(/4), sk and sn rounded
+    # to the vector width); one level as strassen_formed_workspace_size
+    def want(m, n, k, e, v):
+        sm = -(-m // 4)
+        sk = -(-(-(-k // 4)) // v) * v
+        sn = -(-(-(-n // 4)) // v) * v
+        return e * 45 * (sm * sk + sk * sn)
+    f = sg.strassen_formed_workspace_size_ex
+    assert f(16384, 16384, 16384, 2, sg.STRASSEN_F32, sg.STRASSEN_MODE_BF16X3) == 4 * 90 * 4096 * 4096
+    for (m, n, k) in ((15001, 17003, 9007), (3, 5, 7), (1, 1, 1), (3000, 20000, 5000)):
+        assert f(m, n, k, 2, sg.STRASSEN_F32, sg.STRASSEN_MODE_PLAIN) == want(m, n, k, 4, 4)
+        assert f(m, n, k, 2, sg.STRASSEN_BF16, sg.STRASSEN_MODE_PLAIN) == want(m, n, k, 2, 8)
+        assert f(m, n, k, 1, sg.STRASSEN_F16, sg.STRASSEN_MODE_PLAIN) == \
+            sg.strassen_formed_workspace_size(m, n, k, sg.STRASSEN_F16, sg.STRASSEN_MODE_PLAIN)
+    assert f(-1, 1, 1, 2, 0, 0) == -1
+    assert f(1, 1, -1, 2, 0, 0) == -3
+    assert f(1, 1, 1, 0, 0, 0) == -4
+    assert f(1, 1, 1, 3, 0, 0) == -4
+    assert f(1, 1, 1, 2, 7, 0) == -5
+    assert f(1, 1, 1, 2, sg.STRASSEN_BF16, sg.STRASSEN_MODE_BF16X3) == -6
+
+
+def test_formed_ex_validation():
+    need = sg.strassen_formed_workspace_size_ex(64, 64, 64, 2, 0, 0)
+    A, B, C, W = 1 << 20, 1 << 22, 1 << 24, 1 << 26
+    names = ["m", "n", "k", "A", "lda", "a_type", "B", "ldb", "b_type", "C", "ldc", "alpha",
+             "beta", "levels", "mode", "ws", "wsb", "stream"]
+    base = dict(zip(names, [64, 64, 64, A, 64, 0, B, 64, 0, C, 64, 1.0, 1.0, 2, 0, W, need, None]))
+
+    def call(**kw):
+        return sg.strassen_gemm_formed_ex(*dict(base, **kw).values())
+
+    assert call(m=-1) == -1
+    assert call(A=None) == -4
+    assert call(b_type=1) == -9
+    assert call(ldc=3) == -11
+    assert call(levels=0) == -14
+    assert call(levels=3) == -14
+    assert call(mode=4) == -15
+    assert call(ws=None) == -16
+    assert call(wsb=need - 1) == -17
+    assert call(ws=C + 256) == -16        # workspace overlaps C
+
+
 def test_formed_validation():
     need = sg.strassen_formed_workspace_size(64, 64, 64, 0, 0)
     A, B, C, W = 1 << 20, 1 << 22, 1 << 24, 1 << 26

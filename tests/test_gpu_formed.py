@@ -1,6 +1,7 @@
-"""GPU parity of the one-level formed schedule (strassen_gemm_formed): the
-two-term operand sums of eq. gpu_allops formed once into caller workspace,
-then single-term products scattered into C.
+"""GPU parity of the formed schedules (strassen_gemm_formed,
+strassen_gemm_formed_ex): the multi-term operand sums of eq. gpu_allops
+(applied once or twice) formed once into caller workspace, then single-term
+products scattered into C.
 
 * integer inputs: equal to the classical product bit for bit (oracle);
 * real inputs: equal bit for bit to the fused one-level call
@@ -11,6 +12,8 @@ then single-term products scattered into C.
   and C1, C2 stay equal; always within tau_1 of the fp64 oracle at the gate
   eps of the format (bf16x3 at 2^-16: hi + lo carries 16 significant bits;
   its figure at 2^-23 is printed, not gated);
+* two levels: integers exact; real inputs equal bit for bit to the fused
+  two-level call (no chains there, the same batches in the same order);
 * the library allocates nothing; the workspace is the caller's.
 """
 import numpy as np
@@ -28,11 +31,11 @@ FAMILIES = {"f32": ("f32", "plain"), "bf16": ("bf16", "plain"), "f16": ("f16", "
 GATE_EPS = {"f32": 2.0 ** -23, "bf16": 2.0 ** -7, "f16": 2.0 ** -10, "bf16x3": 2.0 ** -16}
 
 
-def _formed(dev, alpha, beta, mode, ws=None):
+def _formed(dev, alpha, beta, mode, ws=None, levels=1):
     A, B, C = dev["A"], dev["B"], dev["C"]
-    print("formed m=%d n=%d k=%d dtype=%s mode=%s" % (A.shape[0], B.shape[1], A.shape[1], A.dtype, mode),
-          flush=True)
-    sg.gemm_formed(A, B, C, alpha=alpha, beta=beta, mode=mode, workspace=ws)
+    print("formed m=%d n=%d k=%d L=%d dtype=%s mode=%s" % (A.shape[0], B.shape[1], A.shape[1], levels, A.dtype,
+                                                           mode), flush=True)
+    sg.gemm_formed(A, B, C, alpha=alpha, beta=beta, mode=mode, workspace=ws, levels=levels)
     torch.cuda.synchronize()
     return C
 
@@ -214,3 +217,79 @@ def test_formed_workspace_errors_on_device():
                                  B.stride(0), sg.STRASSEN_F32, C.data_ptr(), C.stride(0), 1.0, 1.0,
                                  sg.STRASSEN_MODE_PLAIN, ws.data_ptr() + 4, need, None)
     assert rc == -15
+
+
+# ---- two levels (strassen_gemm_formed_ex, levels = 2) ----
+
+@pytest.mark.parametrize("fam", sorted(FAMILIES))
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (3, 5, 7), (65, 67, 63), (257, 130, 300), (1100, 1060, 600)])
+def test_formed2_integer_exact(fam, m, n, k):
+    dtype, mode = FAMILIES[fam]
+    prob = make_problem(m, n, k, kind="integers", dtype=dtype, c_kind="integers")
+    dev = to_device(prob)
+    got = _formed(dev, 1.0, 1.0, mode, levels=2)
+    want = oracle.gemm_f64(prob["A"], prob["B"], prob["C"], 1.0, 1.0)
+    assert np.array_equal(got.cpu().double().numpy(), want)
+
+
+@pytest.mark.parametrize("fam", sorted(FAMILIES))
+def test_formed2_integer_exact_padded_alpha_beta(fam):
+    dtype, mode = FAMILIES[fam]
+    m, n, k = 375, 501, 313
+    prob = make_problem(m, n, k, kind="integers", dtype=dtype, c_kind="integers",
+                        lda=k + 11, ldb=n + 9, ldc=n + 7)
+    dev = to_device(prob)
+    got = _formed(dev, 1.5, 0.5, mode, levels=2)
+    want = oracle.gemm_f64(prob["A"], prob["B"], prob["C"], 1.5, 0.5)
+    assert np.array_equal(got.cpu().double().numpy(), want)
+    assert torch.isnan(dev["C_storage"][:, n:]).all()
+
+
+@pytest.mark.parametrize("fam", sorted(FAMILIES))
+@pytest.mark.parametrize("m,n,k", [(300, 260, 520), (1030, 1100, 1500), (12288, 12288, 512)])
+def test_formed2_equals_fused_two_level(fam, m, n, k):
+    """Four-term sums in the fused kernels' order and precision, the same
+    batches in the same order, single-term products accumulating in the
+    same k order: bit-identical to strassen_gemm_ex at levels = 2 (12288:
+    C blocks of 144 tiles of 256 x 256, the large-tile launches)."""
+    dtype, mode = FAMILIES[fam]
+    prob = make_problem(m, n, k, kind="uniform", dtype=dtype, c_kind="uniform")
+    d1 = to_device(prob)
+    d2 = to_device(prob)
+    assert sg.strassen_profile_start() == 0
+    got = _formed(d1, 1.25, 0.75, mode, levels=2)
+    rc, recs = sg.strassen_profile_stop()
+    names = [r.kernel.decode() for r in recs[:rc]]
+    # 16 product launches (the fused schedule's batches) and one sum-forming
+    # launch per multi-term level-1 operand of A and of B
+    assert sum(not nm.startswith("form_terms") for nm in names) == 16, names
+    assert sum(nm.startswith("form_terms") for nm in names) == 14, names
+    sg.gemm(d2["A"], d2["B"], d2["C"], alpha=1.25, beta=0.75, levels=2, mode=mode)
+    torch.cuda.synchronize()
+    assert torch.equal(got, d2["C"])
+    if m * n <= 2 ** 22:
+        want = oracle.gemm_f64(prob["A"], prob["B"], prob["C"], 1.25, 0.75)
+        en = e_norm(got.cpu().numpy(), want, prob["A"], prob["B"], prob["C"], k, 1.25, 0.75, GATE_EPS[fam])
+        print("e_norm=%.4g (gate eps of %s)" % (en, fam), flush=True)
+        assert en <= tau(2)
+
+
+def test_formed2_workspace_and_errors():
+    m, n, k = 1000, 900, 700
+    sm, sk, sn = 250, 176, 232   # ceil(/4), k and n rounded up to 8 (16-bit) elements
+    assert sg.api.formed_workspace_bytes(m, n, k, torch.bfloat16, "plain", levels=2) == 2 * 45 * (sm * sk + sk * sn)
+    sm, sk, sn = 250, 176, 228   # fp32: rounded up to 4
+    assert sg.api.formed_workspace_bytes(m, n, k, torch.float32, "bf16x3", levels=2) == 4 * 45 * (sm * sk + sk * sn)
+    prob = make_problem(96, 80, 72, kind="uniform", c_kind="uniform")
+    dev = to_device(prob)
+    A, B, C = dev["A"], dev["B"], dev["C"]
+    need = sg.api.formed_workspace_bytes(96, 80, 72, levels=2)
+    ws = torch.empty(need + 64, dtype=torch.uint8, device="cuda")
+    common = (96, 80, 72, A.data_ptr(), A.stride(0), sg.STRASSEN_F32, B.data_ptr(), B.stride(0), sg.STRASSEN_F32,
+              C.data_ptr(), C.stride(0), 1.0, 1.0)
+    for bad in (0, 3):
+        assert sg.strassen_gemm_formed_ex(*common, bad, sg.STRASSEN_MODE_PLAIN, ws.data_ptr(), need, None) == -14
+    assert sg.strassen_gemm_formed_ex(*common, 2, sg.STRASSEN_MODE_PLAIN, ws.data_ptr() + 4, need, None) == -16
+    assert sg.strassen_gemm_formed_ex(*common, 2, sg.STRASSEN_MODE_PLAIN, ws.data_ptr(), need - 16, None) == -17
+    assert sg.strassen_gemm_formed_ex(*common, 2, 7, ws.data_ptr(), need, None) == -15
+    torch.cuda.synchronize()

@@ -157,10 +157,11 @@ def _table(header):
 
 def _launch_prediction(r):
     kind, N, L = KIND[r["kind"]], int(r["N"]), int(r["L"])
-    s = N >> (L if r["schedule"] == "fused" else 1)
+    s = N >> L
     tok = r["kernel"]
-    if tok == "form":
-        return model.form(kind if kind != "f32" else "x3", s, s, 4, 5)
+    m = re.match(r"form \((\d+) > (\d+)\)$", tok)
+    if m:
+        return model.form(kind if kind != "f32" else "x3", s, s, int(m.group(1)), int(m.group(2)))
     m = re.match(r"(\d+) chained (\d+)$", tok)
     if m:
         return model.launch(kind, m.group(1) == "256", 1, 1, 2, s, s, s, int(m.group(2)),
@@ -184,7 +185,7 @@ def test_measured_launches_are_predicted():
             continue
         pred = _launch_prediction(r)
         err = pred / (float(r["measured ms"]) * 1e-3) - 1.0
-        if r["kernel"] == "form":
+        if r["kernel"].startswith("form"):
             groups["form"].append(err)
             continue
         groups["f32" if r["kind"] == "fp32" else "16bit"].append(err)
@@ -200,10 +201,10 @@ def test_measured_launch_workgroups_match_model():
     """The workgroup count the model derives from the shape (tiles per
     product times products, or times chains) equals the recorded one."""
     for r in _table("Launches"):
-        if r["kernel"] == "form":
+        if r["kernel"].startswith("form"):
             continue
         N, L = int(r["N"]), int(r["L"])
-        s = N >> (L if r["schedule"] == "fused" else 1)
+        s = N >> L
         m = re.match(r"(\d+) ", r["kernel"])
         t = int(m.group(1))
         per = math.ceil(s / t) ** 2
