@@ -293,3 +293,27 @@ def test_formed2_workspace_and_errors():
     assert sg.strassen_gemm_formed_ex(*common, 2, sg.STRASSEN_MODE_PLAIN, ws.data_ptr(), need - 16, None) == -17
     assert sg.strassen_gemm_formed_ex(*common, 2, 7, ws.data_ptr(), need, None) == -15
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("fam", ["bf16", "bf16x3"])
+def test_formed2_full_size_equals_fused(fam):
+    """16384^3 (the precision configuration's largest size), two levels:
+    equal to the fused two-level call bit for bit, and stratified entries
+    (every 256 x 256 tile of every C block, block corners, whole 32 x 32
+    accumulator blocks) within tau_2 of the fp64 oracle at the gate eps."""
+    dtype, mode = FAMILIES[fam]
+    N = 16384
+    prob = make_problem(N, N, N, kind="normal", dtype=dtype, c_kind="zeros")
+    dev = to_device(prob)
+    _formed(dev, 1.0, 0.0, mode, levels=2)
+    got = dev["C"].clone()
+    sg.gemm(dev["A"], dev["B"], dev["C"], 1.0, 0.0, levels=2, mode=mode)
+    torch.cuda.synchronize()
+    assert torch.equal(got, dev["C"])
+    rows, cols = stratified_entries(N, N, 2, 2)
+    want = oracle.gemm_entries(prob["A"], prob["B"], None, rows, cols, 1.0, 0.0)
+    g = got[torch.as_tensor(rows, device="cuda"), torch.as_tensor(cols, device="cuda")].double().cpu().numpy()
+    scale = N * float(prob["A"].float().abs().max()) * float(prob["B"].float().abs().max())
+    en = float(np.abs(g - want).max()) / (GATE_EPS[fam] * scale)
+    print("sampled e_norm %.4g at eps=%g, %d entries" % (en, GATE_EPS[fam], len(rows)), flush=True)
+    assert en <= tau(2)
