@@ -337,6 +337,7 @@ int record_end(hipStream_t s, hipEvent_t e0, hipEvent_t e1, const char *kernel, 
 struct SideStream {
     hipStream_t s = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
+    hipEvent_t ready[16] = {};  // formed two-level: one per sum-forming launch
 };
 constexpr int kSideDevices = 64;
 thread_local SideStream g_side[kSideDevices];
@@ -354,6 +355,8 @@ hipError_t side_stream(hipStream_t caller, SideStream **out) {
         err = hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking);
         if (err == hipSuccess) err = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming);
         if (err == hipSuccess) err = hipEventCreateWithFlags(&ss.join, hipEventDisableTiming);
+        for (int i = 0; i < 16 && err == hipSuccess; ++i)
+            err = hipEventCreateWithFlags(&ss.ready[i], hipEventDisableTiming);
         const hipError_t back = cur != dev ? hipSetDevice(cur) : hipSuccess;
         if (err != hipSuccess) return err;
         if (back != hipSuccess) return back;
@@ -827,16 +830,14 @@ int form_operand(const std::vector<FormedSum> &sums, strassen::FormElem fe, size
     return 0;
 }
 
-// Two levels: the sums of one operand X on the 4 x 4 block grid (block
-// (R, Cc) at X + R*srows*ldx + Cc*scols, extents clipped to xr x xc), up to
-// four terms each, one launch per group of sums whose terms lie in the same
-// level-1 quadrants (the operands of one level-1 product: at most seven sums
-// over at most eight blocks, read once from memory per launch).  Records:
-// batch = sums, workgroups = distinct blocks read.
-int form_operand_terms(const std::vector<FormedSum> &sums, strassen::FormElem fe, size_t es, const void *X,
-                       int64_t ldx, int64_t xr, int64_t xc, int64_t srows, int64_t scols, int d, char *out,
-                       bool vec, hipStream_t s, int *launch) {
-    std::vector<std::pair<int, std::vector<int>>> groups;  // level-1 quadrant mask -> sums
+// Two levels: the sums of one operand on the 4 x 4 block grid, grouped for
+// the launches that form them: sums whose terms lie in the same level-1
+// quadrants (the operands of one level-1 product: at most seven sums over
+// at most eight blocks) form one launch, which reads each block once from
+// memory.
+std::vector<std::vector<int>> terms_groups(const std::vector<FormedSum> &sums, int d) {
+    std::vector<int> masks;
+    std::vector<std::vector<int>> groups;
     for (size_t i = 0; i < sums.size(); ++i) {
         int mask = 0;
         for (int t = 0; t < sums[i].nterms; ++t) {
@@ -844,45 +845,134 @@ int form_operand_terms(const std::vector<FormedSum> &sums, strassen::FormElem fe
             mask |= 1 << ((R * 2 / d) * 2 + Cc * 2 / d);
         }
         size_t gi = 0;
-        while (gi < groups.size() && groups[gi].first != mask) ++gi;
-        if (gi == groups.size()) groups.push_back({mask, {}});
-        groups[gi].second.push_back((int)i);
+        while (gi < masks.size() && masks[gi] != mask) ++gi;
+        if (gi == masks.size()) {
+            masks.push_back(mask);
+            groups.emplace_back();
+        }
+        if (groups[gi].size() == (size_t)strassen::kFormTermsMaxOutputs) {  // not reached at two levels
+            masks.push_back(-1);
+            groups.emplace_back();
+            gi = groups.size() - 1;
+        }
+        groups[gi].push_back((int)i);
     }
-    for (const auto &grp : groups) {
-        for (size_t base = 0; base < grp.second.size(); base += strassen::kFormTermsMaxOutputs) {
-            const size_t nout = std::min(grp.second.size() - base, (size_t)strassen::kFormTermsMaxOutputs);
-            strassen::FormTermsOut o[strassen::kFormTermsMaxOutputs];
-            std::vector<int> blocks;
-            for (size_t j = 0; j < nout; ++j) {
-                const int i = grp.second[base + j];
-                const FormedSum &f = sums[i];
-                o[j].ptr = out + (uint64_t)i * srows * scols * es;
-                o[j].n = f.nterms;
-                o[j].pad = 0;
-                for (int t = 0; t < f.nterms; ++t) {
-                    const int R = f.t[t].block / d, Cc = f.t[t].block % d;
-                    o[j].src[t].ptr = static_cast<const char *>(X) + ((uint64_t)R * srows * ldx + (uint64_t)Cc * scols) * es;
-                    o[j].src[t].rows = (int32_t)strassen::block_extent(xr, srows, R);
-                    o[j].src[t].cols = (int32_t)strassen::block_extent(xc, scols, Cc);
-                    o[j].s[t] = (float)f.t[t].sign;
-                    if (std::find(blocks.begin(), blocks.end(), f.t[t].block) == blocks.end())
-                        blocks.push_back(f.t[t].block);
-                }
-            }
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            bool timed = false;
-            int rc = record_begin(s, &e0, &e1, &timed);
-            if (rc != 0) return rc;
-            const hipError_t err = strassen::launch_form_terms(fe, o, (int)nout, ldx, scols, srows, scols, vec, s);
-            if (err != hipSuccess) return (int)err;
-            if (timed) {
-                rc = record_end(s, e0, e1, fe == strassen::FormElem::kF32 ? "form_terms<f32>" : "form_terms<16-bit>",
-                                *launch, (int)nout, (int)blocks.size(), 0.0);
-                if (rc != 0) return rc;
-            }
-            ++*launch;
+    return groups;
+}
+
+// One group of sums of operand X (block (R, Cc) at X + R*srows*ldx +
+// Cc*scols, extents clipped to xr x xc) into `out` (sum i at
+// i*srows*scols elements, dense, leading dimension scols).  Record: batch =
+// sums, workgroups = distinct blocks read.
+int form_terms_group(const std::vector<int> &group, const std::vector<FormedSum> &sums, strassen::FormElem fe,
+                     size_t es, const void *X, int64_t ldx, int64_t xr, int64_t xc, int64_t srows, int64_t scols,
+                     int d, char *out, bool vec, hipStream_t s, int launch) {
+    strassen::FormTermsOut o[strassen::kFormTermsMaxOutputs];
+    std::vector<int> blocks;
+    const size_t nout = group.size();
+    for (size_t j = 0; j < nout; ++j) {
+        const int i = group[j];
+        const FormedSum &f = sums[i];
+        o[j].ptr = out + (uint64_t)i * srows * scols * es;
+        o[j].n = f.nterms;
+        o[j].pad = 0;
+        for (int t = 0; t < f.nterms; ++t) {
+            const int R = f.t[t].block / d, Cc = f.t[t].block % d;
+            o[j].src[t].ptr = static_cast<const char *>(X) + ((uint64_t)R * srows * ldx + (uint64_t)Cc * scols) * es;
+            o[j].src[t].rows = (int32_t)strassen::block_extent(xr, srows, R);
+            o[j].src[t].cols = (int32_t)strassen::block_extent(xc, scols, Cc);
+            o[j].s[t] = (float)f.t[t].sign;
+            if (std::find(blocks.begin(), blocks.end(), f.t[t].block) == blocks.end())
+                blocks.push_back(f.t[t].block);
         }
     }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool timed = false;
+    int rc = record_begin(s, &e0, &e1, &timed);
+    if (rc != 0) return rc;
+    const hipError_t err = strassen::launch_form_terms(fe, o, (int)nout, ldx, scols, srows, scols, vec, s);
+    if (err != hipSuccess) return (int)err;
+    if (timed)
+        return record_end(s, e0, e1, fe == strassen::FormElem::kF32 ? "form_terms<f32>" : "form_terms<16-bit>",
+                          launch, (int)nout, (int)blocks.size(), 0.0);
+    return 0;
+}
+
+// Two levels: the sum-forming launches in the order of their first use by
+// the batches, on a side stream when `side` (each batch waits for the
+// launches it reads), the batches in the fused schedule's order on the
+// caller's stream, so the result is the fused one's.
+template <class RunBatch>
+int run_formed_batches_2(const Call &c, const FormedGeom &g, strassen::FormElem fe, size_t in_es, char *wa,
+                         char *wb, bool vec_a, bool vec_b, bool side, int &launch, RunBatch &run_batch) {
+    const Plan &plan = g.plan;
+    const int d = plan.d;
+    const std::vector<std::vector<int>> ga = terms_groups(g.asums, d), gb = terms_groups(g.bsums, d);
+    std::vector<int> a_group(g.asums.size(), -1), b_group(g.bsums.size(), -1);
+    for (size_t gi = 0; gi < ga.size(); ++gi)
+        for (int i : ga[gi]) a_group[i] = (int)gi;
+    for (size_t gi = 0; gi < gb.size(); ++gi)
+        for (int i : gb[gi]) b_group[i] = (int)gi;
+    // form launches in first-use order; per batch, the last one it reads
+    std::vector<std::pair<int, int>> order;  // (operand 0 = A / 1 = B, group)
+    std::vector<int> pos_a(ga.size(), -1), pos_b(gb.size(), -1), wait(plan.batches.size(), -1);
+    for (size_t bi = 0; bi < plan.batches.size(); ++bi) {
+        for (int pi : plan.batches[bi].products) {
+            if (g.a_of[pi] >= 0) {
+                int &p = pos_a[a_group[g.a_of[pi]]];
+                if (p < 0) {
+                    p = (int)order.size();
+                    order.push_back({0, a_group[g.a_of[pi]]});
+                }
+                wait[bi] = std::max(wait[bi], p);
+            }
+            if (g.b_of[pi] >= 0) {
+                int &p = pos_b[b_group[g.b_of[pi]]];
+                if (p < 0) {
+                    p = (int)order.size();
+                    order.push_back({1, b_group[g.b_of[pi]]});
+                }
+                wait[bi] = std::max(wait[bi], p);
+            }
+        }
+    }
+    const Plan &pl = plan;
+    auto form = [&](size_t k, hipStream_t s) {
+        const int op = order[k].first, gi = order[k].second;
+        return op == 0 ? form_terms_group(ga[gi], g.asums, fe, in_es, c.A, c.lda, c.m, c.k, pl.sm, pl.sk, d, wa,
+                                          vec_a, s, (int)k)
+                       : form_terms_group(gb[gi], g.bsums, fe, in_es, c.B, c.ldb, c.k, c.n, pl.sk, pl.sn, d, wb,
+                                          vec_b, s, (int)k);
+    };
+    SideStream *ss = nullptr;
+    if (side && order.size() <= 16) {
+        const hipError_t err = side_stream(c.stream, &ss);
+        if (err != hipSuccess) return (int)err;
+    }
+    int rc = 0;
+    launch = (int)order.size();
+    if (ss == nullptr) {
+        for (size_t k = 0; k < order.size(); ++k)
+            if ((rc = form(k, c.stream)) != 0) return rc;
+        for (size_t bi = 0; bi < plan.batches.size(); ++bi)
+            if ((rc = run_batch(bi)) != 0) return rc;
+        return 0;
+    }
+    hipError_t err = hipEventRecord(ss->fork, c.stream);
+    if (err == hipSuccess) err = hipStreamWaitEvent(ss->s, ss->fork, 0);
+    if (err != hipSuccess) return (int)err;
+    for (size_t k = 0; k < order.size(); ++k) {
+        if ((rc = form(k, ss->s)) != 0) return rc;
+        if ((err = hipEventRecord(ss->ready[k], ss->s)) != hipSuccess) return (int)err;
+    }
+    if ((err = hipEventRecord(ss->join, ss->s)) != hipSuccess) return (int)err;
+    for (size_t bi = 0; bi < plan.batches.size(); ++bi) {
+        if (wait[bi] >= 0 && (err = hipStreamWaitEvent(c.stream, ss->ready[wait[bi]], 0)) != hipSuccess)
+            return (int)err;
+        if ((rc = run_batch(bi)) != 0) return rc;
+    }
+    // the caller's stream waits for every sum-forming launch
+    if ((err = hipStreamWaitEvent(c.stream, ss->join, 0)) != hipSuccess) return (int)err;
     return 0;
 }
 
@@ -1162,18 +1252,11 @@ int run_formed(const Call &c, void *ws, bool side = true) {
             if ((rc = run_batch(bi)) != 0) return rc;
         return 0;
     }
-    if (plan.levels == 1) {
-        rc = form_operand(g.asums, fe, in_es, c.A, c.lda, c.m, c.k, sm, sk, wa, vec_a, c.stream, 0);
-        if (rc != 0) return rc;
-        rc = form_operand(g.bsums, fe, in_es, c.B, c.ldb, c.k, c.n, sk, sn, wb, vec_b, c.stream, 1);
-        if (rc != 0) return rc;
-    } else {
-        launch = 0;
-        rc = form_operand_terms(g.asums, fe, in_es, c.A, c.lda, c.m, c.k, sm, sk, d, wa, vec_a, c.stream, &launch);
-        if (rc != 0) return rc;
-        rc = form_operand_terms(g.bsums, fe, in_es, c.B, c.ldb, c.k, c.n, sk, sn, d, wb, vec_b, c.stream, &launch);
-        if (rc != 0) return rc;
-    }
+    if (plan.levels == 2) return run_formed_batches_2(c, g, fe, in_es, wa, wb, vec_a, vec_b, side, launch, run_batch);
+    rc = form_operand(g.asums, fe, in_es, c.A, c.lda, c.m, c.k, sm, sk, wa, vec_a, c.stream, 0);
+    if (rc != 0) return rc;
+    rc = form_operand(g.bsums, fe, in_es, c.B, c.ldb, c.k, c.n, sk, sn, wb, vec_b, c.stream, 1);
+    if (rc != 0) return rc;
     for (size_t bi = 0; bi < plan.batches.size(); ++bi)
         if ((rc = run_batch(bi)) != 0) return rc;
     return 0;

@@ -200,6 +200,32 @@ def predict(m, n, k, levels, kind="f32"):
     return sum(l["seconds"] for l in launches), launches
 
 
+def predict_formed(m, n, k, levels, kind="f32"):
+    """Predicted seconds of one formed call (strassen_gemm_formed_ex), its
+    launches one after another: the sum-forming launches (one level: one per
+    operand, four quadrants into five sums; two levels: per operand five
+    launches of eight blocks into seven sums and two of four into five),
+    then the single-term products in the fused schedule's batches (the
+    one-level 16-bit chains, which save a C update and a launch, are not
+    modelled).  Returns (total_seconds, [per-launch dicts or seconds])."""
+    dt = {"f32": B.STRASSEN_F32, "16bit": B.STRASSEN_BF16, "x3": B.STRASSEN_F32}[kind]
+    mode = B.STRASSEN_MODE_BF16X3 if kind == "x3" else B.STRASSEN_MODE_PLAIN
+    rc, info = B.strassen_plan_info(m, n, k, levels, dt, mode)
+    if rc != 0:
+        raise ValueError("plan_info failed (%d)" % rc)
+    sm, sn, sk = info.sub_m, info.sub_n, info.sub_k
+    if levels == 1:
+        forms = [form(kind, sm, sk, 4, 5), form(kind, sk, sn, 4, 5)]
+    else:
+        forms = [form(kind, rows, cols, src, out) for rows, cols in ((sm, sk), (sk, sn))
+                 for src, out in [(8, 7)] * 5 + [(4, 5)] * 2]
+    launches = []
+    for wa, wb, wc, batch in _batches(levels):
+        large = _use_large(sm, sn, sk, batch, kind == "f32")
+        launches.append(launch(kind, large, 1, 1, wc, sm, sn, sk, batch))
+    return sum(forms) + sum(l["seconds"] for l in launches), forms + launches
+
+
 def parse_kernel(name):
     """(kind, large, (W_A, W_B, W_C) or None, chains or 0) from a launch
     record's kernel name; kind None for the sum-forming kernels."""

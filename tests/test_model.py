@@ -172,8 +172,9 @@ def _launch_prediction(r):
 
 
 def test_measured_launches_are_predicted():
-    """Every launch of at least 0.05 ms (the side-stream form excepted, whose
-    event time includes the batch it overlaps): 16-bit and compensated
+    """Every launch of at least 0.05 ms (the sum-forming launches on a side
+    stream and the products they share the GPU with excepted: their event
+    times include the overlap): 16-bit and compensated
     product launches within 27 % and at least 95 % of them within 25 %;
     fp32 launches at least 95 % within 25 %; the formed schedule's
     sum-forming launches within 35 %."""
@@ -181,7 +182,7 @@ def test_measured_launches_are_predicted():
     assert len(rows) > 250
     groups = {"16bit": [], "f32": [], "form": []}
     for r in rows:
-        if r["note"] == "side":
+        if r["note"] in ("side", "overlap"):
             continue
         pred = _launch_prediction(r)
         err = pred / (float(r["measured ms"]) * 1e-3) - 1.0
@@ -226,3 +227,19 @@ def test_measured_calls_are_predicted_at_4096_and_above():
             assert abs(t / (float(r["measured ms"]) * 1e-3) - 1.0) <= 0.20, r
             checked += 1
     assert checked == 27
+
+
+def test_measured_formed_calls_are_predicted_at_4096_and_above():
+    """Whole formed calls (sums formed first, then single-term products) at
+    m = n = k >= 4096: the model's launches one after another within 20 %
+    of the measured call, which overlaps forms with products."""
+    rows = _table("Formed calls")
+    assert len(rows) == 25
+    checked = 0
+    for r in rows:
+        N = int(r["N"])
+        t, _ = model.predict_formed(N, N, N, int(r["levels"]), KIND[r["kind"]])
+        if N >= 4096:
+            assert abs(t / (float(r["measured ms"]) * 1e-3) - 1.0) <= 0.20, r
+            checked += 1
+    assert checked == 15
