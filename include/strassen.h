@@ -153,7 +153,12 @@ int64_t strassen_hybrid_workspace_size(int64_t m, int64_t n, int64_t k);
  * bytes, 16-byte aligned, overlapping none of A, B, C; owned by the caller,
  * contents undefined after the call; may be NULL when the product term is
  * absent (m, n or k = 0, or alpha = 0).  Calls that overlap on one workspace
- * race.  Enqueued on hip_stream (NULL = the null stream).
+ * race.  Enqueued on hip_stream (NULL = the null stream); where the chains
+ * apply, B's sums are formed on a second stream of the calling thread
+ * (created on first use per device, default priority, kept until the
+ * thread ends) beside the products that read B as stored, ordered by
+ * events, and hip_stream waits for that stream before the call returns, so
+ * to the caller the call is ordered on hip_stream like any other.
  * Argument indices: m=1 n=2 k=3 A=4 lda=5 a_type=6 B=7 ldb=8 b_type=9 C=10
  * ldc=11 alpha=12 beta=13 mode=14 workspace=15 workspace_bytes=16
  * hip_stream=17.  Overlap of A or B with C reports -10. */
@@ -183,7 +188,11 @@ int64_t strassen_formed_workspace_size(int64_t m, int64_t n, int64_t k,
  * stored values, 16-bit data rounded once); then the 49 products run the
  * single-term kernel in the race-free batches and the launch order of
  * strassen_gemm_ex at levels = 2, so the result equals that call's bit for
- * bit.  At one level the same as strassen_gemm_formed.  Arguments as
+ * bit.  The sum-forming launches run on the calling thread's second stream
+ * (as for strassen_gemm_formed) in the order the batches first read them,
+ * each batch waiting for its sums through an event, so forms overlap the
+ * products of earlier batches; hip_stream waits for that stream before the
+ * call returns.  At one level the same as strassen_gemm_formed.  Arguments as
  * strassen_gemm_formed with levels inserted: m=1 n=2 k=3 A=4 lda=5 a_type=6
  * B=7 ldb=8 b_type=9 C=10 ldc=11 alpha=12 beta=13 levels=14 mode=15
  * workspace=16 workspace_bytes=17 hip_stream=18. */
