@@ -317,3 +317,23 @@ def test_formed2_full_size_equals_fused(fam):
     en = float(np.abs(g - want).max()) / (GATE_EPS[fam] * scale)
     print("sampled e_norm %.4g at eps=%g, %d entries" % (en, GATE_EPS[fam], len(rows)), flush=True)
     assert en <= tau(2)
+
+
+def _random_shapes(count, seed):
+    rng = np.random.default_rng(seed)
+    return [tuple(int(v) for v in rng.integers(1, 700, 3)) for _ in range(count)]
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+@pytest.mark.parametrize("fam", sorted(FAMILIES))
+def test_formed_random_shapes_integer_exact(fam, levels):
+    """Twelve seeded random shapes up to 700 per dimension (ragged blocks,
+    virtual padding in every operand), alpha 1.5, beta 0.5: exact against
+    the classical product."""
+    dtype, mode = FAMILIES[fam]
+    for (m, n, k) in _random_shapes(12, 1000 * levels + len(fam)):
+        prob = make_problem(m, n, k, kind="integers", dtype=dtype, c_kind="integers")
+        dev = to_device(prob)
+        got = _formed(dev, 1.5, 0.5, mode, levels=levels)
+        want = oracle.gemm_f64(prob["A"], prob["B"], prob["C"], 1.5, 0.5)
+        assert np.array_equal(got.cpu().double().numpy(), want), (m, n, k)
