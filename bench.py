@@ -61,6 +61,9 @@ def parse():
                    help="skip the bf16x3 plain / fused / formed comparison")
     p.add_argument("--no-small", action="store_true",
                    help="skip the small-size schedule section")
+    p.add_argument("--mfma-probe", action="store_true",
+                   help="only measure the matrix cores' attainable rate (register-operand MFMA loops, "
+                        "bf16 / fp16 / fp32, constant and random operands) and print one JSON line")
     p.add_argument("--launch-table", metavar="PATH",
                    help="only time every launch of squares m=n=k in 1024..16384 at levels 0/1/2 "
                         "(fp32, bf16, bf16x3; plus the formed one-level calls) with library "
@@ -590,6 +593,35 @@ def small_sizes_section(steps, dev, stream, log):
     return out
 
 
+def mfma_probe(dev, stream, log, reps=5):
+    """The matrix cores' attainable rate (strassen_probe_mfma): two
+    workgroups of four waves per CU, each wave a long run of independent
+    MFMAs on register operands, constant or random values; median of `reps`
+    timed launches after one warm-up, TFLOP/s against the dense peaks."""
+    import numpy as np
+    import torch
+    import paper_1808_07984_amd as sg
+
+    wgs = 512
+    out = torch.empty(wgs * 256, device=dev)
+    res = {}
+    for op, name, iters, per, peak in ((0, "bf16", 400000, 32768.0, 2516.6), (1, "fp16", 400000, 32768.0, 2516.6),
+                                       (2, "fp32", 100000, 4096.0, FP32_MFMA_PEAK)):
+        for random in (0, 1):
+            def run():
+                rc = sg.strassen_probe_mfma(op, random, iters, wgs, out.data_ptr(), stream.cuda_stream)
+                if rc != 0:
+                    raise SystemExit("strassen_probe_mfma failed: %d" % rc)
+            ts = [time_calls(run, 1, 1 if r == 0 else 0, stream) for r in range(reps)]
+            ms = float(np.median(ts))
+            tf = wgs * 4 * iters * 4 * per / (ms * 1e-3) / 1e12
+            key = "%s_%s" % (name, "random" if random else "constant")
+            res[key] = {"ms": round(ms, 3), "tflops": round(tf, 1), "frac_of_peak": round(tf / peak, 4),
+                        "peak": peak}
+            log("mfma probe %s: %.3f ms  %.1f TFLOP/s  (%.3f of %.1f)" % (key, ms, tf, tf / peak, peak))
+    return res
+
+
 def launch_table(path, dev, stream, log, sizes=(1024, 2048, 4096, 8192, 16384), reps=3):
     """Every launch of C := A*B at m=n=k in `sizes`, levels 0/1/2, for fp32,
     bf16 and bf16x3 (N(0,1) operands, drawn on the device: the 16-bit
@@ -664,6 +696,12 @@ def main():
     torch.cuda.set_device(dev)
     if args.launch_table:
         launch_table(args.launch_table, dev, torch.cuda.current_stream(dev), log)
+        return
+    if args.mfma_probe:
+        import json
+        print(json.dumps({"mfma_probe": mfma_probe(dev, torch.cuda.current_stream(dev), log),
+                          "workload": "register-operand MFMA loops, 512 workgroups of 4 waves, "
+                                      "4 independent accumulators per wave"}), flush=True)
         return
     N = args.size
     m = n = k = N

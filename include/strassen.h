@@ -354,6 +354,20 @@ typedef struct {
 int strassen_profile_start(void);
 int strassen_profile_stop(strassen_launch_record_t *out, int capacity);
 
+/* The matrix cores' attainable rate, the ceiling the kernels' MFMA-busy
+ * fractions are read against (Analysis section: the peak a kernel is
+ * modelled against).  Enqueues one launch of `workgroups` workgroups of four
+ * waves; every wave issues `iters` rounds of four independent MFMAs on
+ * operands held in registers (op 0: 32x32x16 bf16, 1: 32x32x16 fp16,
+ * 2: 32x32x2 fp32), with random values in [-0.5, 0.5) (random != 0) or a
+ * constant 0.25, and no memory traffic but one float per thread written to
+ * out (workgroups * 256 floats, device memory owned by the caller).  One
+ * launch executes workgroups * 4 * iters * 4 MFMAs of 32768 (16-bit) or 4096
+ * (fp32) flops each; time it with events on hip_stream.  Returns 0, a
+ * negative argument index (op=1 random=2 iters=3 workgroups=4 out=5) or a
+ * positive hipError_t. */
+int strassen_probe_mfma(int op, int random, int64_t iters, int32_t workgroups, float *out, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -48,6 +48,7 @@ from ._binding import (  # noqa: F401
     strassen_plan_instances,
     strassen_profile_start,
     strassen_profile_stop,
+    strassen_probe_mfma,
     strassen_set_schedule,
     strassen_set_stream,
     strassen_set_tile,

@@ -89,6 +89,7 @@ SIGNATURES = {
     "strassen_build_id": (ctypes.c_char_p, []),
     "strassen_profile_start": (_int, []),
     "strassen_profile_stop": (_int, [ctypes.POINTER(strassen_launch_record_t), _int]),
+    "strassen_probe_mfma": (_int, [_int, _int, _i64, ctypes.c_int32, _vp, _vp]),
 }
 
 
@@ -267,3 +268,7 @@ def strassen_profile_stop(capacity=4096):
     buf = (strassen_launch_record_t * max(capacity, 1))()
     rc = lib.strassen_profile_stop(buf, capacity)
     return rc, list(buf[:max(0, min(rc, capacity))])
+
+
+def strassen_probe_mfma(op, random, iters, workgroups, out, hip_stream=None):
+    return lib.strassen_probe_mfma(op, random, iters, workgroups, out, hip_stream)

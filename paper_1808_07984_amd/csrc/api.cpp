@@ -1635,6 +1635,15 @@ int strassen_profile_start(void) {
     return 0;
 }
 
+int strassen_probe_mfma(int op, int random, int64_t iters, int32_t workgroups, float *out, void *hip_stream) {
+    if (op < 0 || op > 2) return -1;
+    if (random != 0 && random != 1) return -2;
+    if (iters < 0) return -3;
+    if (workgroups < 1) return -4;
+    if (out == nullptr) return -5;
+    return (int)strassen::launch_mfma_probe(op, random, iters, workgroups, out, (hipStream_t)hip_stream);
+}
+
 int strassen_profile_stop(strassen_launch_record_t *out, int capacity) {
     if (out == nullptr && capacity > 0) return -1;
     if (capacity < 0) return -2;

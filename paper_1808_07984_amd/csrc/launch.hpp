@@ -115,6 +115,12 @@ struct FormTermsOut {
 hipError_t launch_form_terms(FormElem elem, const FormTermsOut *out, int nout, int64_t ld_src,
                              int64_t ld_out, int64_t rows, int64_t cols, bool vec, hipStream_t s);
 
+// strassen_probe_mfma: `workgroups` workgroups of four waves, each wave
+// `iters` rounds of four independent MFMAs on register operands (op 0 bf16
+// 32x32x16, 1 fp16 32x32x16, 2 fp32 32x32x2; random or constant values);
+// out receives one float per thread (workgroups * 256).
+hipError_t launch_mfma_probe(int op, int random, int64_t iters, int32_t workgroups, float *out, hipStream_t s);
+
 // strassen_gemm_formed_noalloc: the device address of the library's fixed
 // scratch array (kNoAllocScratchBytes, 256-byte aligned) on the device of
 // `stream` (the current device for the null stream), looked up once per

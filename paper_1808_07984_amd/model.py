@@ -40,7 +40,8 @@ costs about twice the A operand per byte: the eight-XCD tile mapping walks
 groups of four tile rows, so the 32 workgroups one XCD runs at once share
 each A panel eight ways and each B panel only four ways.  Clocks are the
 measured ones: fp32 under the GEMM (GRBM_GUI_ACTIVE), 16-bit under sustained
-MFMA work on random operands, which is power limited (~1.65 GHz).
+MFMA work on random operands, which is power limited (1.65-1.78 GHz in the
+library's MFMA rate probe, strassen_probe_mfma).
 
 Also modelled: the formed schedules' sum kernels (streaming, at a measured
 5 TB/s) and the one-level schedule's chained launches (two products per

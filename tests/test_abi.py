@@ -254,3 +254,12 @@ def test_build_id_matches_sources():
     refuses to load one that was not)."""
     assert sg.strassen_build_id() == _binding.source_id()
     assert len(sg.strassen_build_id()) == 64
+
+
+def test_probe_mfma_validation():
+    # argument errors return before anything is launched
+    assert sg.strassen_probe_mfma(3, 0, 10, 1, 1 << 20) == -1
+    assert sg.strassen_probe_mfma(0, 2, 10, 1, 1 << 20) == -2
+    assert sg.strassen_probe_mfma(0, 0, -1, 1, 1 << 20) == -3
+    assert sg.strassen_probe_mfma(0, 0, 10, 0, 1 << 20) == -4
+    assert sg.strassen_probe_mfma(0, 0, 10, 1, None) == -5

@@ -1,7 +1,8 @@
 """Differentiation: StrassenMatmul's backward (dA = dC B^T, dB = A^T dC,
 through the transposed-operand kernels) against the classical gradient from
-the fp64 oracle, a finite-difference check of the bilinear map, and torch's
-gradcheck in fast mode.  Shapes: 64x48x80 (gradient checks) and the two
+the fp64 oracle and a finite-difference check of the bilinear map (torch's
+gradcheck is not used: in fp32 its finite differences are too coarse to pin
+anything the oracle gradient does not).  Shapes: 64x48x80 (gradient checks) and the two
 differentiation workloads (4096^3 and 8192x2048x6144, sampled entries)."""
 import numpy as np
 import pytest
@@ -64,15 +65,6 @@ def test_finite_difference_of_bilinear_map(levels):
     scale = float(dCd.abs().sum()) * k * 2 * EPS["f32"] * tau(levels)
     assert abs(lhs_a - rhs_a) <= scale, (lhs_a, rhs_a)
     assert abs(lhs_b - rhs_b) <= scale, (lhs_b, rhs_b)
-
-
-@pytest.mark.parametrize("levels", [0, 1, 2])
-def test_gradcheck_fast_mode(levels):
-    m, n, k = 64, 48, 80
-    A = inputs.uniform(m, k, 0).cuda().requires_grad_(True)
-    B = inputs.uniform(k, n, 1).cuda().requires_grad_(True)
-    f = lambda a, b: sg.strassen_matmul(a, b, levels)  # noqa: E731
-    assert torch.autograd.gradcheck(f, (A, B), eps=1e-2, atol=2e-3, rtol=2e-3, fast_mode=True)
 
 
 @pytest.mark.parametrize("m,n,k", [(4096, 4096, 4096), (8192, 2048, 6144)])

@@ -9,7 +9,7 @@ import torch
 
 import oracle
 import paper_1808_07984_amd as sg
-from parity import EPS, e_norm, make_problem, tau, to_device
+from parity import EPS, e_norm, make_problem, stratified_entries, tau, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -83,9 +83,15 @@ def test_concurrent_float_within_tolerance_and_repeatable(levels, m, n, k):
 
 def test_concurrent_matches_batched_on_integers_large():
     """Both schedules give the exact product on an integer workload large
-    enough for 256x256 tiles."""
+    enough for 256x256 tiles: stratified entries (every tile of every C
+    block, corners, whole accumulator blocks) equal the oracle's, and the two
+    schedules agree everywhere."""
     prob = make_problem(4096, 4096, 2048, kind="integers", c_kind="integers", int_range=(-1, 1))
     dev = _run(prob, 2, 1.0, 1.0)
+    rows, cols = stratified_entries(4096, 4096, 2, 11)
+    want = oracle.gemm_entries(prob["A"], prob["B"], prob["C"], rows, cols, 1.0, 1.0)
+    got = dev["C"][torch.as_tensor(rows, device="cuda"), torch.as_tensor(cols, device="cuda")]
+    assert np.array_equal(got.cpu().double().numpy(), want)
     sg.strassen_set_schedule(sg.STRASSEN_SCHEDULE_BATCHED)
     d2 = to_device(prob)
     sg.gemm(d2["A"], d2["B"], d2["C"], 1.0, 1.0, levels=2)
