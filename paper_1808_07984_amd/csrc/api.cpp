@@ -745,6 +745,10 @@ int run_hybrid(const Call &c, float *ws) {
 // single-output products M5 and M6 are accumulated after M2 and M3 and added
 // into C3 and C0 together with them, saving two read-modify-writes of a C
 // block and a launch, and those two blocks can differ in the last bits.
+// Two levels: the same for the 49 products on the 4 x 4 block grid, whose
+// operands are up to four-term sums (formed by the general-term kernel, one
+// launch per level-1 operand), without chains, the batches in the fused
+// schedule's order: the result is the fused two-level result bit for bit.
 // ---------------------------------------------------------------------------
 struct FormedSum {
     int nterms;
