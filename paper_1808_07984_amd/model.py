@@ -36,9 +36,12 @@ levels 0/1/2 (fp32, bf16 and the compensated mode, fused and formed).  They are 
 of latency-bound loads, not bandwidths: the sixteen-bit kernels reach about
 a third of their MFMA peak on the plain product, and their multi-term launches
 are set by how many operand bytes a CU can keep in flight.  The B operand
-costs about twice the A operand per byte: the eight-XCD tile mapping walks
-groups of four tile rows, so the 32 workgroups one XCD runs at once share
-each A panel eight ways and each B panel only four ways.  Clocks are the
+(n-contiguous, staged through the paired layout) costs about twice the A
+operand per byte.  That is not the tile walk's panel sharing (the 32
+workgroups one XCD runs at once are 4 tile rows x 8 columns, so each A panel
+is shared eight ways and each B panel four): walking groups of eight rows
+instead, which reverses the sharing, left the B-heavy compensated launches
+unchanged (-0.4 to -0.6 %, results identical).  Clocks are the
 measured ones: fp32 under the GEMM (GRBM_GUI_ACTIVE), 16-bit under sustained
 MFMA work on random operands, which is power limited (1.65-1.78 GHz in the
 library's MFMA rate probe, strassen_probe_mfma).
