@@ -30,7 +30,7 @@ measured on MI355X:
 * a launch costs the sum of its rounds, at least its algorithmic HBM bytes
   over 8 TB/s, plus a launch overhead.
 
-R_A, R_B, R_C, T_round and the 0.9 factor of the 128 x 128 tile's operand
+R_A, R_B, R_C, T_round and the 0.85 factor of the 128 x 128 tile's operand
 rates are fitted to the event times of every launch of squares 1024-16384 at
 levels 0/1/2 (fp32, bf16 and the compensated mode, fused and formed).  They are per-CU rates
 of latency-bound loads, not bandwidths: the sixteen-bit kernels reach about
@@ -61,11 +61,11 @@ MFMA_FLOP_PER_CLK_CU = {"f32": 256.0, "16bit": 4096.0}
 LDS_WRITE_B_PER_CLK_CU = 128.0
 LDS_READ_B_PER_CLK_CU = 256.0
 VALU_OPS_PER_CLK_CU = 64.0   # 4 SIMDs x 16 lanes
-R_A_B_PER_S_CU = 60e9        # A-operand bytes per second per CU (fitted)
-R_B_B_PER_S_CU = 31e9        # B-operand bytes per second per CU (fitted)
-R_C_B_PER_S_CU = 24e9        # epilogue C bytes per second per CU (fitted)
-SMALL_TILE_FETCH = 0.9       # 128x128 tile: operand time factor (fitted)
-ROUND_S = 6e-6               # fixed cost per round of workgroups (fitted)
+R_A_B_PER_S_CU = 58e9        # A-operand bytes per second per CU (fitted)
+R_B_B_PER_S_CU = 29e9        # B-operand bytes per second per CU (fitted)
+R_C_B_PER_S_CU = 26e9        # epilogue C bytes per second per CU (fitted)
+SMALL_TILE_FETCH = 0.85      # 128x128 tile: operand time factor (fitted)
+ROUND_S = 7e-6               # fixed cost per round of workgroups (fitted)
 FORM_B_PER_S = 5.0e12        # sum-forming kernels, bytes read + written (measured)
 HBM_B_PER_S = 8.0e12
 LAUNCH_S = 6e-6
