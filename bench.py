@@ -698,7 +698,6 @@ def main():
         launch_table(args.launch_table, dev, torch.cuda.current_stream(dev), log)
         return
     if args.mfma_probe:
-        import json
         print(json.dumps({"mfma_probe": mfma_probe(dev, torch.cuda.current_stream(dev), log),
                           "workload": "register-operand MFMA loops, 512 workgroups of 4 waves, "
                                       "4 independent accumulators per wave"}), flush=True)
