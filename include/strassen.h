@@ -146,7 +146,13 @@ int64_t strassen_hybrid_workspace_size(int64_t m, int64_t n, int64_t k);
  * C0 together with them (one read-modify-write of those blocks fewer each),
  * so those two blocks can differ from the fused result in the last bits.
  * Worth it where staging multi-term sums inside the product kernel is the
- * bottleneck (the BF16X3 mode).  A and B as stored (no transposes);
+ * bottleneck (the BF16X3 mode).  In the BF16X3 mode the sums are stored
+ * pre-split (per four consecutive elements the bf16 hi parts, then the bf16
+ * lo parts, rounded as the kernels split a staged value), and so are A's two
+ * single quadrants that products take as operands (A00 of M2, A11 of M3), so
+ * every product stages A without splitting it, and B too where B is a sum;
+ * the LDS contents, and so the results, are those of the fp32 sums.  A and B
+ * as stored (no transposes);
  * a_type == b_type; modes and types as in strassen_gemm_ex; same degenerate
  * cases.
  * workspace: device memory of at least strassen_formed_workspace_size()
@@ -172,9 +178,11 @@ int strassen_gemm_formed(int64_t m, int64_t n, int64_t k,
 /* Workspace bytes strassen_gemm_formed needs: e * (5 sm sk + 5 sk sn) with
  * the one-level block extents sm = ceil(m/2), sk = ceil(k/2), sn = ceil(n/2)
  * (sk and sn rounded up to the 16-byte vector width: 4 fp32 or 8 16-bit
- * elements) and e = 2 bytes for bf16/fp16 data, 4 for fp32 data in either
- * mode; about 1.25 (mk + kn) e bytes.  Returns the size, or a negative
- * argument index (m=1 n=2 k=3 dtype=4 mode=5).  Pure host computation. */
+ * elements) and e = 2 bytes for bf16/fp16 data, 4 for fp32 data in the
+ * PLAIN mode; about 1.25 (mk + kn) e bytes.  BF16X3 mode: 4 * (7 sm sk +
+ * 5 sk sn) (A's two single quadrants stored pre-split too).  Returns the
+ * size, or a negative argument index (m=1 n=2 k=3 dtype=4 mode=5).  Pure
+ * host computation. */
 int64_t strassen_formed_workspace_size(int64_t m, int64_t n, int64_t k,
                                        strassen_dtype_t dtype, strassen_mode_t mode);
 
@@ -185,7 +193,9 @@ int64_t strassen_formed_workspace_size(int64_t m, int64_t n, int64_t k,
  * grid) is formed once into workspace, one launch per level-1 operand
  * reading its at most eight blocks once, with the fused kernels' arithmetic
  * (terms added in order, one fused multiply-add each, in fp32 from the
- * stored values, 16-bit data rounded once); then the 49 products run the
+ * stored values, 16-bit data rounded once; in the BF16X3 mode stored
+ * pre-split as at one level, together with the four single blocks of each
+ * operand); then the 49 products run the
  * single-term kernel in the race-free batches and the launch order of
  * strassen_gemm_ex at levels = 2, so the result equals that call's bit for
  * bit.  The sum-forming launches run on the calling thread's second stream
@@ -206,7 +216,9 @@ int strassen_gemm_formed_ex(int64_t m, int64_t n, int64_t k,
 /* Workspace bytes strassen_gemm_formed_ex needs: at one level as
  * strassen_formed_workspace_size; at two levels e * 45 (sm sk + sk sn) with
  * the two-level block extents sm = ceil(m/4), sk = ceil(k/4), sn = ceil(n/4)
- * (sk, sn rounded up as above), about 2.8 (mk + kn) e bytes.  Returns the
+ * (sk, sn rounded up as above), about 2.8 (mk + kn) e bytes; BF16X3 mode
+ * 4 * 49 (sm sk + sk sn) (the four single blocks of each operand that
+ * products take stored pre-split too).  Returns the
  * size, or a negative argument index (m=1 n=2 k=3 levels=4 dtype=5 mode=6).
  * Pure host computation. */
 int64_t strassen_formed_workspace_size_ex(int64_t m, int64_t n, int64_t k, int levels,

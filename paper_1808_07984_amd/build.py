@@ -22,7 +22,7 @@ LIB = os.path.join(OUT_DIR, "libstrassen.so")
 ARCH = "gfx950"
 
 SOURCES = ["api.cpp", "plan.cpp", "scale.hip", "form.hip", "noalloc.hip", "probe.hip", "gemm_f32_dispatch.cpp", "gemm_m16_dispatch.cpp",
-           "gemm_bf16.hip", "gemm_f16.hip"] + [
+           "gemm_bf16.hip", "gemm_f16.hip", "gemm_bf16x3p_nn.hip"] + [
     "gemm_bf16x3_%s.hip" % lay for lay in ("nn", "nt", "tn", "tt")] + [
     "gemm_f32_%s_%s.hip" % (lay, tile) for lay in ("nn", "nt", "tn", "tt") for tile in ("s", "l")]
 

@@ -761,6 +761,12 @@ struct FormedGeom {
     std::vector<int> a_of, b_of;          // per product: its sum, or -1
     size_t es = 4;                        // bytes per workspace element
     int64_t a_bytes = 0, bytes = 0;
+    // Compensated mode: the workspace operands are written pre-split, and
+    // the single blocks that products take as operands too -- A's at one
+    // level (B's single quadrants are read as stored by the products that
+    // run beside B's form), A's and B's at two levels -- so that products
+    // stage pre-split operands.
+    bool pre = false;
 };
 
 int find_or_add(std::vector<FormedSum> &sums, const strassen::Term *t, int n) {
@@ -780,9 +786,11 @@ int find_or_add(std::vector<FormedSum> &sums, const strassen::Term *t, int n) {
 FormedGeom formed_geom(int64_t m, int64_t n, int64_t k, const Family &fam, int levels) {
     FormedGeom g;
     g.plan = strassen::make_plan(m, n, k, levels, fam.vec);
+    g.pre = fam.m16 && fam.op == strassen::Operand16::kBf16x3;
+    const bool b_singles = g.pre && levels == 2;
     for (const strassen::Product &p : g.plan.products) {
-        g.a_of.push_back(p.na > 1 ? find_or_add(g.asums, p.a, p.na) : -1);
-        g.b_of.push_back(p.nb > 1 ? find_or_add(g.bsums, p.b, p.nb) : -1);
+        g.a_of.push_back(p.na > 1 || g.pre ? find_or_add(g.asums, p.a, p.na) : -1);
+        g.b_of.push_back(p.nb > 1 || b_singles ? find_or_add(g.bsums, p.b, p.nb) : -1);
     }
     g.es = (fam.m16 && fam.op != strassen::Operand16::kBf16x3) ? 2 : 4;
     const Plan &pl = g.plan;
@@ -829,7 +837,10 @@ int form_operand(const std::vector<FormedSum> &sums, strassen::FormElem fe, size
                                                       srows, scols, vec, s);
     if (err != hipSuccess) return (int)err;
     if (timed)
-        return record_end(s, e0, e1, fe == strassen::FormElem::kF32 ? "form_sums<f32>" : "form_sums<16-bit>",
+        return record_end(s, e0, e1,
+                          fe == strassen::FormElem::kF32        ? "form_sums<f32>"
+                          : fe == strassen::FormElem::kX3Split ? "form_sums<x3split>"
+                                                               : "form_sums<16-bit>",
                           launch, (int)sums.size(), (int)(srows < 65536 ? srows : 65536), 0.0);
     return 0;
 }
@@ -897,7 +908,10 @@ int form_terms_group(const std::vector<int> &group, const std::vector<FormedSum>
     const hipError_t err = strassen::launch_form_terms(fe, o, (int)nout, ldx, scols, srows, scols, vec, s);
     if (err != hipSuccess) return (int)err;
     if (timed)
-        return record_end(s, e0, e1, fe == strassen::FormElem::kF32 ? "form_terms<f32>" : "form_terms<16-bit>",
+        return record_end(s, e0, e1,
+                          fe == strassen::FormElem::kF32        ? "form_terms<f32>"
+                          : fe == strassen::FormElem::kX3Split ? "form_terms<x3split>"
+                                                               : "form_terms<16-bit>",
                           launch, (int)nout, (int)blocks.size(), 0.0);
     return 0;
 }
@@ -994,7 +1008,8 @@ int run_formed(const Call &c, void *ws, bool side = true) {
     const size_t in_es = elem_size(c.a_type);
     char *wa = static_cast<char *>(ws);
     char *wb = wa + g.a_bytes;
-    const strassen::FormElem fe = g.es == 4                       ? strassen::FormElem::kF32
+    const strassen::FormElem fe = g.pre                           ? strassen::FormElem::kX3Split
+                                  : g.es == 4                     ? strassen::FormElem::kF32
                                   : c.a_type == STRASSEN_BF16 ? strassen::FormElem::kBf16
                                                               : strassen::FormElem::kF16;
     const bool vec_a = (c.lda % fam.vec == 0) && ((uintptr_t)c.A % 16 == 0);
@@ -1069,6 +1084,12 @@ int run_formed(const Call &c, void *ws, bool side = true) {
                 all = all && found;
             }
             if (!all) continue;
+            if (g.pre) {  // the chained kernel takes pre-split operands only
+                bool pre_b = true;
+                for (size_t q = 0; q < pick.size(); ++q)
+                    if (pick[q] >= 0) pre_b = pre_b && g.b_of[q] >= 0 && g.b_of[pick[q]] >= 0;
+                if (!pre_b) continue;
+            }
             bool reads_b_sums = false;
             for (int x : bt.products) reads_b_sums = reads_b_sums || g.b_of[x] >= 0;
             const int score = 2 * (int)bt.products.size() + (reads_b_sums ? 1 : 0);
@@ -1143,11 +1164,14 @@ int run_formed(const Call &c, void *ws, bool side = true) {
             bool timed = false;
             rc = record_begin(c.stream, &e0, &e1, &timed);
             if (rc != 0) return rc;
-            const hipError_t err = strassen::launch_m16_chained(fam.op, a, nchains, vec, c.stream);
+            const hipError_t err = g.pre ? strassen::launch_m16_x3pre_chained(a, nchains, vec, c.stream)
+                                         : strassen::launch_m16_chained(fam.op, a, nchains, vec, c.stream);
             if (err != hipSuccess) return (int)err;
             if (timed) {
                 char name[64];
-                std::snprintf(name, sizeof(name), "%s<chained,%d,%s>", strassen::m16_kernel_name(fam.op, true),
+                std::snprintf(name, sizeof(name), "%s<chained,%d,%s>",
+                              g.pre ? strassen::m16_x3pre_kernel_name(true, true)
+                                    : strassen::m16_kernel_name(fam.op, true),
                               nchains, vec ? "vec" : "scalar");
                 rc = record_end(c.stream, e0, e1, name, launch, 2 * nchains, a.tiles_m * a.tiles_n * nchains,
                                 2.0 * (double)(2 * nchains) * (double)sm * (double)sn * (double)sk);
@@ -1197,13 +1221,16 @@ int run_formed(const Call &c, void *ws, bool side = true) {
             rc = record_begin(c.stream, &e0, &e1, &timed);
             if (rc != 0) return rc;
             const hipError_t err =
-                fam.m16 ? strassen::launch_m16(fam.op, false, false, large, 1, 1, bt.wc, a, batch, vec, c.stream)
-                        : strassen::launch_f32(false, false, large, 1, 1, bt.wc, a, batch, vec, c.stream);
+                g.pre     ? strassen::launch_m16_x3pre(fb, large, 1, 1, bt.wc, a, batch, vec, c.stream)
+                : fam.m16 ? strassen::launch_m16(fam.op, false, false, large, 1, 1, bt.wc, a, batch, vec, c.stream)
+                          : strassen::launch_f32(false, false, large, 1, 1, bt.wc, a, batch, vec, c.stream);
             if (err != hipSuccess) return (int)err;
             if (timed) {
                 char name[64];
                 std::snprintf(name, sizeof(name), "%s<1,1,%d,%s>",
-                              fam.m16 ? strassen::m16_kernel_name(fam.op, large) : strassen::f32_kernel_name(large),
+                              g.pre     ? strassen::m16_x3pre_kernel_name(fb, large)
+                              : fam.m16 ? strassen::m16_kernel_name(fam.op, large)
+                                        : strassen::f32_kernel_name(large),
                               bt.wc, vec ? "vec" : "scalar");
                 rc = record_end(c.stream, e0, e1, name, launch, batch, a.tiles_m * a.tiles_n * batch,
                                 2.0 * (double)batch * (double)sm * (double)sn * (double)sk);

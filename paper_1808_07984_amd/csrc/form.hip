@@ -96,6 +96,32 @@ struct Elem<FormElem::kF16> {
     __device__ static unsigned short put(float x) { return __builtin_bit_cast(unsigned short, (_Float16)x); }
 };
 
+// fp32 sources, outputs pre-split for the compensated mode (written by
+// store_split, not put).
+template <>
+struct Elem<FormElem::kX3Split> {
+    static constexpr int NV = 4;
+    using In = float;
+    __device__ static float get(float x) { return x; }
+};
+
+// Four sums, pre-split: hi_e = bf16(s_e) and lo_e = bf16(s_e - hi_e), both
+// rounded to nearest even (the compensated kernels' split of a staged value),
+// stored as the words (hi_0 | hi_1 << 16, hi_2 | hi_3 << 16, lo_0 | lo_1 << 16,
+// lo_2 | lo_3 << 16).
+__device__ __forceinline__ void store_split(float *dst, const float (&s)[4]) {
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    const unsigned h01 = __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{s[0], s[1]}, bf16x2));
+    const unsigned h23 = __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{s[2], s[3]}, bf16x2));
+    const float r0 = s[0] - __uint_as_float(h01 << 16), r1 = s[1] - __uint_as_float(h01 & 0xffff0000u);
+    const float r2 = s[2] - __uint_as_float(h23 << 16), r3 = s[3] - __uint_as_float(h23 & 0xffff0000u);
+    const unsigned l01 = __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{r0, r1}, bf16x2));
+    const unsigned l23 = __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{r2, r3}, bf16x2));
+    *reinterpret_cast<u32x4 *>(dst) = u32x4{h01, h23, l01, l23};
+}
+
 template <FormElem E, bool VEC>
 __global__ __launch_bounds__(256) void form_sums_kernel(const SumsArgs a) {
     using T = Elem<E>;
@@ -129,7 +155,7 @@ __global__ __launch_bounds__(256) void form_sums_kernel(const SumsArgs a) {
             for (int o = 0; o < kFormMaxOutputs; ++o) {
                 if (o >= a.nout) break;
                 const FormOut fo = a.out[o];
-                Vec v;
+                float sv[NV];
 #pragma unroll
                 for (int e = 0; e < NV; ++e) {
                     float s = 0.f;
@@ -143,9 +169,17 @@ __global__ __launch_bounds__(256) void form_sums_kernel(const SumsArgs a) {
                             if (q == fo.t1) y = x[q][e];
                         s = __builtin_fmaf(fo.s1, y, s);
                     }
-                    v[e] = T::put(s);
+                    sv[e] = s;
                 }
-                *reinterpret_cast<Vec *>(static_cast<In *>(fo.ptr) + r * a.ld_out + c) = v;
+                In *dst = static_cast<In *>(fo.ptr) + r * a.ld_out + c;
+                if constexpr (E == FormElem::kX3Split) {
+                    store_split(dst, sv);
+                } else {
+                    Vec v;
+#pragma unroll
+                    for (int e = 0; e < NV; ++e) v[e] = T::put(sv[e]);
+                    *reinterpret_cast<Vec *>(dst) = v;
+                }
             }
         }
     }
@@ -207,7 +241,7 @@ __global__ __launch_bounds__(256) void form_terms_kernel(const TermsArgs a) {
     for (int64_t r = blockIdx.x; r < a.rows; r += gridDim.x) {
         for (int64_t u = threadIdx.x; u < units; u += blockDim.x) {
             const int64_t c = u * NV;
-            constexpr bool kAhead = E == FormElem::kF32;
+            constexpr bool kAhead = E == FormElem::kF32 || E == FormElem::kX3Split;
             Vec cur[kFormTermsMax], nxt[kFormTermsMax];
             if constexpr (kAhead) load_terms<T, VEC, NV, Vec>(a.out[0], r, c, a.ld_src, cur);
 #pragma unroll
@@ -231,10 +265,15 @@ __global__ __launch_bounds__(256) void form_terms_kernel(const TermsArgs a) {
 #pragma unroll
                     for (int e = 0; e < NV; ++e) acc[e] = __builtin_fmaf(st, T::get(cur[t][e]), acc[e]);
                 }
-                Vec v;
+                In *dst = static_cast<In *>(fo.ptr) + r * a.ld_out + c;
+                if constexpr (E == FormElem::kX3Split) {
+                    store_split(dst, acc);
+                } else {
+                    Vec v;
 #pragma unroll
-                for (int e = 0; e < NV; ++e) v[e] = T::put(acc[e]);
-                *reinterpret_cast<Vec *>(static_cast<In *>(fo.ptr) + r * a.ld_out + c) = v;
+                    for (int e = 0; e < NV; ++e) v[e] = T::put(acc[e]);
+                    *reinterpret_cast<Vec *>(dst) = v;
+                }
                 if (kAhead && o + 1 < a.nout) {
 #pragma unroll
                     for (int t = 0; t < kFormTermsMax; ++t) cur[t] = nxt[t];
@@ -275,7 +314,7 @@ namespace strassen {
 hipError_t launch_form_sums(FormElem elem, const FormSource *src, int nsrc, int64_t ld_src,
                             const FormOut *out, int nout, int64_t ld_out, int64_t rows, int64_t cols,
                             bool vec, hipStream_t s) {
-    const int nv = elem == FormElem::kF32 ? 4 : 8;
+    const int nv = (elem == FormElem::kF32 || elem == FormElem::kX3Split) ? 4 : 8;
     if (nsrc < 1 || nsrc > kFormMaxSources || nout < 1 || nout > kFormMaxOutputs || cols % nv != 0 ||
         ld_out % nv != 0 || rows < 0)
         return hipErrorInvalidValue;
@@ -306,6 +345,10 @@ hipError_t launch_form_sums(FormElem elem, const FormSource *src, int nsrc, int6
             if (vec) hipLaunchKernelGGL((form_sums_kernel<FormElem::kF16, true>), dim3(blocks), dim3(256), 0, s, a);
             else hipLaunchKernelGGL((form_sums_kernel<FormElem::kF16, false>), dim3(blocks), dim3(256), 0, s, a);
             break;
+        case FormElem::kX3Split:
+            if (vec) hipLaunchKernelGGL((form_sums_kernel<FormElem::kX3Split, true>), dim3(blocks), dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((form_sums_kernel<FormElem::kX3Split, false>), dim3(blocks), dim3(256), 0, s, a);
+            break;
     }
     return hipGetLastError();
 }
@@ -316,7 +359,7 @@ namespace strassen {
 
 hipError_t launch_form_terms(FormElem elem, const FormTermsOut *out, int nout, int64_t ld_src,
                              int64_t ld_out, int64_t rows, int64_t cols, bool vec, hipStream_t s) {
-    const int nv = elem == FormElem::kF32 ? 4 : 8;
+    const int nv = (elem == FormElem::kF32 || elem == FormElem::kX3Split) ? 4 : 8;
     if (nout < 1 || nout > kFormTermsMaxOutputs || cols % nv != 0 || ld_out % nv != 0 || rows < 0)
         return hipErrorInvalidValue;
     for (int o = 0; o < nout; ++o)
@@ -343,6 +386,10 @@ hipError_t launch_form_terms(FormElem elem, const FormTermsOut *out, int nout, i
         case FormElem::kF16:
             if (vec) hipLaunchKernelGGL((form_terms_kernel<FormElem::kF16, true>), dim3(blocks), dim3(256), 0, s, a);
             else hipLaunchKernelGGL((form_terms_kernel<FormElem::kF16, false>), dim3(blocks), dim3(256), 0, s, a);
+            break;
+        case FormElem::kX3Split:
+            if (vec) hipLaunchKernelGGL((form_terms_kernel<FormElem::kX3Split, true>), dim3(blocks), dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((form_terms_kernel<FormElem::kX3Split, false>), dim3(blocks), dim3(256), 0, s, a);
             break;
     }
     return hipGetLastError();

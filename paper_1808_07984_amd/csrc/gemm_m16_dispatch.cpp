@@ -53,4 +53,9 @@ const char *m16_kernel_name(Operand16 op, bool large) {
     return "strassen_m16_kernel";
 }
 
+const char *m16_x3pre_kernel_name(bool pre_b, bool large) {
+    if (pre_b) return large ? "strassen_m16_kernel<bf16x3p,256x256>" : "strassen_m16_kernel<bf16x3p,128x128>";
+    return large ? "strassen_m16_kernel<bf16x3pa,256x256>" : "strassen_m16_kernel<bf16x3pa,128x128>";
+}
+
 }  // namespace strassen

@@ -70,6 +70,7 @@ struct Bf16Ops {
     using Vec = u16x8;          // one 16-byte load
     static constexpr int NV = 8;
     static constexpr bool kX3 = false;
+    static constexpr bool kPreA = false, kPreB = false;
     __device__ static float to_f32(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
     __device__ static unsigned short from_f32(float f) {
         return __builtin_bit_cast(unsigned short, (__bf16)f);
@@ -84,6 +85,7 @@ struct F16Ops {
     using Vec = u16x8;
     static constexpr int NV = 8;
     static constexpr bool kX3 = false;
+    static constexpr bool kPreA = false, kPreB = false;
     __device__ static float to_f32(unsigned short h) {
         return (float)__builtin_bit_cast(_Float16, h);
     }
@@ -99,6 +101,7 @@ struct X3Ops {
     using Vec = f32x4;
     static constexpr int NV = 4;
     static constexpr bool kX3 = true;
+    static constexpr bool kPreA = false, kPreB = false;
     __device__ static float to_f32(float x) { return x; }
     __device__ static unsigned short from_f32(float f) {
         return __builtin_bit_cast(unsigned short, (__bf16)f);
@@ -109,6 +112,20 @@ struct X3Ops {
     __device__ static unsigned pack2(float lo, float hi) {
         return __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{lo, hi}, bf16x2));
     }
+};
+
+// The compensated mode on operands already split ("pre-split", written by the
+// formed schedule's sum pass): every 16-byte unit holds four consecutive
+// elements as hi(e0..e3) in its first 8 bytes and lo(e0..e3) in its last 8
+// (bf16 each, element e at 16-bit position e of its half), so an operand has
+// the fp32 operand's size, strides and alignment, and staging it is moving
+// the two halves into the two LDS planes -- the same LDS contents the split
+// of the fp32 value gives.  kPreA / kPreB: which operand is pre-split (the
+// other one is fp32 and split while staged).  Pre-split operands need
+// 16-byte aligned units (cols and leading dimension multiples of 4).
+template <bool PA, bool PB>
+struct X3PreOps : X3Ops {
+    static constexpr bool kPreA = PA, kPreB = PB;
 };
 
 // Staging geometry of one operand (X = MT or NT rows of the [x][k] tile).
@@ -179,7 +196,10 @@ struct Stage {
 // Loads NV consecutive elements of a block starting at (line, run), zero
 // outside lines x runs.  fast: the whole run is inside and aligned.  Lanes
 // whose elements are outside never access memory.
-template <class Ops>
+// PRE: a pre-split operand (whole 16-byte units only: a unit that crosses the
+// extent is loaded whole and its hi and lo halves of the elements outside are
+// cleared).
+template <class Ops, bool PRE = false>
 __device__ __forceinline__ typename Ops::Vec load_vec(const typename Ops::In *__restrict__ base,
                                                       int64_t ld, int line, int run, int lines,
                                                       int runs, bool fast, bool vec) {
@@ -189,6 +209,22 @@ __device__ __forceinline__ typename Ops::Vec load_vec(const typename Ops::In *__
 #pragma unroll
     for (int e = 0; e < NV; ++e) v[e] = 0;
     const typename Ops::In *p = base + (int64_t)line * ld + run;
+    if constexpr (PRE) {
+        static_assert(NV == 4, "pre-split units hold four elements");
+        if (fast || (line < lines && run + NV - 1 < runs)) return *reinterpret_cast<const V *>(p);
+        if (line < lines && run < runs) {
+            u32x4 w = __builtin_bit_cast(u32x4, *reinterpret_cast<const V *>(p));
+#pragma unroll
+            for (int e = 0; e < NV; ++e)
+                if (run + e >= runs) {
+                    const unsigned keep = (e & 1) ? 0x0000ffffu : 0xffff0000u;
+                    w[e >> 1] &= keep;
+                    w[2 + (e >> 1)] &= keep;
+                }
+            v = __builtin_bit_cast(V, w);
+        }
+        return v;
+    }
     if (fast || (line < lines && vec && run + NV - 1 < runs)) {
         v = *reinterpret_cast<const V *>(p);
     } else if (line < lines) {
@@ -214,6 +250,8 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
     constexpr int NPLANES = Ops::kX3 ? 2 : 1;  // hi (and lo) tiles
     using SA = Stage<C, Ops, C::MT, A_KC, WA == 1>;
     using SB = Stage<C, Ops, C::NT, B_KC, WB == 1>;
+    static_assert(!Ops::kPreA || (A_KC && WA == 1), "pre-split A: single term, stored as is");
+    static_assert(!Ops::kPreB || (!B_KC && WB == 1), "pre-split B: single term, stored as is");
     __shared__ __attribute__((aligned(16))) unsigned short As[2][NPLANES][SA::SIZE];
     __shared__ __attribute__((aligned(16))) unsigned short Bs[2][NPLANES][SB::SIZE];
 
@@ -257,10 +295,11 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
     // along k; XC (paired units): element (x, k) at off + k*ld + x, vectors
     // along x, two consecutive k rows per unit.
     auto load_operand = [&](auto &raw, const In *base, const TermArg *terms, auto stage, auto kc,
-                            auto nterms, int64_t ld, int x0, int k0, bool fast) __attribute__((always_inline)) {
+                            auto nterms, int64_t ld, int x0, int k0, bool fast, auto pre) __attribute__((always_inline)) {
         using S = decltype(stage);
         constexpr bool KC = decltype(kc)::value;
         constexpr int NT_ = decltype(nterms)::value;
+        constexpr bool PRE = decltype(pre)::value;
 #pragma unroll
         for (int p = 0; p < S::VECS; ++p) {
             int x, k;
@@ -274,8 +313,8 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
                     const int run = KC ? k0 + k : x0 + x;
                     const int lines = KC ? terms[t].rows : terms[t].cols;
                     const int runs = KC ? terms[t].cols : terms[t].rows;
-                    raw[t][p][l] = load_vec<Ops>(base + terms[t].off, ld, line, run, lines, runs,
-                                                 fast, vec != 0);
+                    raw[t][p][l] = load_vec<Ops, PRE>(base + terms[t].off, ld, line, run, lines, runs,
+                                                      fast, vec != 0);
                 }
         }
     };
@@ -287,7 +326,8 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
         const bool fast = vec && a_x_full && b_x_full && (k0 + C::KT <= a_k) && (k0 + C::KT <= b_k);
         // A terms carry (rows, cols) = (m, k) = (x, k) extents
         load_operand(raw_a, A, P.a, SA{}, std::integral_constant<bool, A_KC>{},
-                     std::integral_constant<int, WA>{}, lda, row0, k0, fast);
+                     std::integral_constant<int, WA>{}, lda, row0, k0, fast,
+                     std::integral_constant<bool, Ops::kPreA>{});
         // B terms carry (rows, cols) = (k, n): swap to (x, k) extents
         TermArg bt[WB];
 #pragma unroll
@@ -297,7 +337,8 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
             bt[t].cols = P.b[t].rows;
         }
         load_operand(raw_b, B, bt, SB{}, std::integral_constant<bool, B_KC>{},
-                     std::integral_constant<int, WB>{}, ldb, col0, k0, fast);
+                     std::integral_constant<int, WB>{}, ldb, col0, k0, fast,
+                     std::integral_constant<bool, Ops::kPreB>{});
     };
 
     // In-bounds k-tiles [0, nfast): unguarded loads from a uniform per-term
@@ -464,6 +505,11 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
             SA::coords(tid, p, x, k);
             if constexpr (A_KC && kCopyA) {
                 *reinterpret_cast<V *>(&As[buf][0][x * SA::LDX + k]) = ra[0][p][0];
+            } else if constexpr (A_KC && Ops::kPreA) {
+                // pre-split: the unit's halves are the hi and lo rows of NV k
+                const u32x4 w = __builtin_bit_cast(u32x4, ra[0][p][0]);
+                *reinterpret_cast<u32x2 *>(&As[buf][0][x * SA::LDX + k]) = u32x2{w[0], w[1]};
+                *reinterpret_cast<u32x2 *>(&As[buf][1][x * SA::LDX + k]) = u32x2{w[2], w[3]};
             } else if constexpr (A_KC) {
                 // direct: NV consecutive k of row x
                 unsigned short hi[NV], lo[NV];
@@ -551,6 +597,21 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
                 for (int e = 0; e < NV; ++e)
                     *reinterpret_cast<unsigned *>(&Bs[buf][0][base + e * SB::LDX]) =
                         pair_words(rb[0][p][0], rb[0][p][1], e);
+            } else if constexpr (Ops::kPreB) {
+                // pre-split rows k and k+1 of NV consecutive x: the word of
+                // x + e in each plane pairs element e's halves of both rows
+                const int base = SB::at(x, k);
+                const u32x4 r0 = __builtin_bit_cast(u32x4, rb[0][p][0]);
+                const u32x4 r1 = __builtin_bit_cast(u32x4, rb[0][p][1]);
+#pragma unroll
+                for (int e = 0; e < NV; ++e) {
+                    const unsigned sel = (e & 1) ? 0x07060302u : 0x05040100u;
+                    const int off = base + e * SB::LDX;
+                    *reinterpret_cast<unsigned *>(&Bs[buf][0][off]) =
+                        __builtin_amdgcn_perm(r1[e >> 1], r0[e >> 1], sel);
+                    *reinterpret_cast<unsigned *>(&Bs[buf][1][off]) =
+                        __builtin_amdgcn_perm(r1[2 + (e >> 1)], r0[2 + (e >> 1)], sel);
+                }
             } else {
                 const int base = SB::at(x, k);
 #pragma unroll
@@ -1100,6 +1161,20 @@ hipError_t dispatch(int wa, int wb, int wc, const LaunchArgs &a, int batch, bool
     STRASSEN_CASE(2, 4, 2)
     STRASSEN_CASE(4, 2, 2)
 #undef STRASSEN_CASE
+    return hipErrorInvalidValue;
+}
+
+// Pre-split compensated operands (the formed one-level schedule, A and B as
+// stored): single-term products with one, two or four outputs.
+template <class C, class Ops>
+hipError_t dispatch_pre(int wa, int wb, int wc, const LaunchArgs &a, int batch, bool vec, hipStream_t s) {
+    using T = TileFor<C, Ops, 1, 1, true, false>;
+    if (wa != 1 || wb != 1) return hipErrorInvalidValue;
+    switch (wc) {
+        case 1: return launch_variant<T, Ops, true, false, 1, 1, 1>(a, batch, vec, s);
+        case 2: return launch_variant<T, Ops, true, false, 1, 1, 2>(a, batch, vec, s);
+        case 4: return launch_variant<T, Ops, true, false, 1, 1, 4>(a, batch, vec, s);
+    }
     return hipErrorInvalidValue;
 }
 

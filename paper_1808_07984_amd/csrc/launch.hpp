@@ -64,6 +64,16 @@ hipError_t launch_m16_bf16_chained(const LaunchArgs &a, int nchains, bool vec, h
 hipError_t launch_m16_f16_chained(const LaunchArgs &a, int nchains, bool vec, hipStream_t s);
 hipError_t launch_m16_bf16x3_chained(const LaunchArgs &a, int nchains, bool vec, hipStream_t s);
 
+// The compensated mode on pre-split operands (four elements per 16-byte unit:
+// their bf16 hi parts, then their bf16 lo parts; written by launch_form_sums
+// with FormElem::kX3Split), A and B as stored, single-term products (W_A =
+// W_B = 1, W_C in {1, 2, 4}): A pre-split, B pre-split (pre_b) or fp32.
+// Chained launches: both pre-split, 256x256 tiles.
+hipError_t launch_m16_x3pre(bool pre_b, bool large, int wa, int wb, int wc, const LaunchArgs &a, int batch,
+                            bool vec, hipStream_t s);
+hipError_t launch_m16_x3pre_chained(const LaunchArgs &a, int nchains, bool vec, hipStream_t s);
+const char *m16_x3pre_kernel_name(bool pre_b, bool large);
+
 // Hybrid top level: out[r][c] = sum_t sign_t * src_t[r * ld_src + c], zero
 // where r >= rows_t or c >= cols_t; out is rows x cols (cols % 4 == 0) with
 // leading dimension ld_out (% 4 == 0), 16-byte aligned.  1 or 2 terms.
@@ -82,8 +92,11 @@ hipError_t launch_form(float *out, int64_t ld_out, int64_t rows, int64_t cols, i
 // outside its rows x cols extent is zero.  Outputs are dense (ld_out), cols
 // and ld_out multiples of the 16-byte unit (4 fp32 or 8 16-bit elements),
 // 16-byte aligned; vec = sources aligned for 16-byte loads.
-enum class FormElem { kF32, kBf16, kF16 };
-constexpr int kFormMaxSources = 4, kFormMaxOutputs = 5;
+// FormElem::kX3Split: fp32 sources, each output written pre-split for the
+// compensated mode (per four elements x: bf16 hi = x rounded to nearest even,
+// then bf16 lo = (x - hi) rounded to nearest even; see launch_m16_x3pre).
+enum class FormElem { kF32, kBf16, kF16, kX3Split };
+constexpr int kFormMaxSources = 4, kFormMaxOutputs = 7;
 struct FormSource {
     const void *ptr;
     int32_t rows, cols;

@@ -207,8 +207,11 @@ def predict(m, n, k, levels, kind="f32"):
 def predict_formed(m, n, k, levels, kind="f32"):
     """Predicted seconds of one formed call (strassen_gemm_formed_ex), its
     launches one after another: the sum-forming launches (one level: one per
-    operand, four quadrants into five sums; two levels: per operand five
-    launches of eight blocks into seven sums and two of four into five),
+    operand, four quadrants into five sums, seven of A in the compensated
+    mode, whose single quadrants are stored pre-split too; two levels: per
+    operand five
+    launches of eight blocks into seven sums and two of four into five, or
+    into seven with the two single blocks in the compensated mode),
     then the single-term products in the fused schedule's batches (the
     one-level 16-bit chains, which save a C update and a launch, are not
     modelled).  Returns (total_seconds, [per-launch dicts or seconds])."""
@@ -219,10 +222,10 @@ def predict_formed(m, n, k, levels, kind="f32"):
         raise ValueError("plan_info failed (%d)" % rc)
     sm, sn, sk = info.sub_m, info.sub_n, info.sub_k
     if levels == 1:
-        forms = [form(kind, sm, sk, 4, 5), form(kind, sk, sn, 4, 5)]
+        forms = [form(kind, sm, sk, 4, 7 if kind == "x3" else 5), form(kind, sk, sn, 4, 5)]
     else:
         forms = [form(kind, rows, cols, src, out) for rows, cols in ((sm, sk), (sk, sn))
-                 for src, out in [(8, 7)] * 5 + [(4, 5)] * 2]
+                 for src, out in [(8, 7)] * 5 + [(4, 7 if kind == "x3" else 5)] * 2]
     launches = []
     for wa, wb, wc, batch in _batches(levels):
         large = _use_large(sm, sn, sk, batch, kind == "f32")
@@ -254,7 +257,7 @@ def predict_record(kernel, batch, workgroups, sm, sn, sk, kind_hint=None):
         fk = "16bit" if "16-bit" in kernel else "x3"
         if kernel.startswith("form_terms"):
             return form(kind_hint or fk, sm, sk, workgroups, batch)
-        return form(kind_hint or fk, sm, sk, 4, 5)
+        return form(kind_hint or fk, sm, sk, 4, batch)
     if chains:
         return launch(kind, large, 1, 1, 2, sm, sn, sk, chains, products_per_workgroup=2)["seconds"]
     return launch(kind, large, *variant, sm, sn, sk, batch)["seconds"]

@@ -152,17 +152,19 @@ def test_hybrid_validation():
 
 def test_formed_workspace_size():
     # e * (5 sm sk + 5 sk sn), one-level extents, sk and sn rounded to the
-    # 16-byte vector width (4 fp32, 8 16-bit elements)
-    def want(m, n, k, e, v):
+    # 16-byte vector width (4 fp32, 8 16-bit elements); the compensated mode
+    # stores A's two single quadrants (pre-split) too: 4 * (7 sm sk + 5 sk sn)
+    def want(m, n, k, e, v, na=5):
         sm = -(-m // 2)
         sk = -(-(-(-k // 2)) // v) * v
         sn = -(-(-(-n // 2)) // v) * v
-        return e * (5 * sm * sk + 5 * sk * sn)
+        return e * (na * sm * sk + 5 * sk * sn)
     f = sg.strassen_formed_workspace_size
-    assert f(16384, 16384, 16384, sg.STRASSEN_F32, sg.STRASSEN_MODE_BF16X3) == 4 * 10 * 8192 * 8192
+    assert f(16384, 16384, 16384, sg.STRASSEN_F32, sg.STRASSEN_MODE_BF16X3) == 4 * 12 * 8192 * 8192
+    assert f(16384, 16384, 16384, sg.STRASSEN_F32, sg.STRASSEN_MODE_PLAIN) == 4 * 10 * 8192 * 8192
     for (m, n, k) in ((15001, 17003, 9007), (3, 5, 7), (1, 1, 1), (3000, 20000, 5000)):
         assert f(m, n, k, sg.STRASSEN_F32, sg.STRASSEN_MODE_PLAIN) == want(m, n, k, 4, 4)
-        assert f(m, n, k, sg.STRASSEN_F32, sg.STRASSEN_MODE_BF16X3) == want(m, n, k, 4, 4)
+        assert f(m, n, k, sg.STRASSEN_F32, sg.STRASSEN_MODE_BF16X3) == want(m, n, k, 4, 4, na=7)
         assert f(m, n, k, sg.STRASSEN_BF16, sg.STRASSEN_MODE_PLAIN) == want(m, n, k, 2, 8)
         assert f(m, n, k, sg.STRASSEN_F16, sg.STRASSEN_MODE_PLAIN) == want(m, n, k, 2, 8)
     assert f(-1, 1, 1, 0, 0) == -1
@@ -174,16 +176,20 @@ def test_formed_workspace_size():
 
 def test_formed_workspace_size_two_levels():
     # e * 45 (sm sk + sk sn), two-level extents (ceil(/4), sk and sn rounded
-    # to the vector width); one level as strassen_formed_workspace_size
-    def want(m, n, k, e, v):
+    # to the vector width), 49 blocks per operand in the compensated mode
+    # (its single blocks stored pre-split too); one level as
+    # strassen_formed_workspace_size
+    def want(m, n, k, e, v, nb=45):
         sm = -(-m // 4)
         sk = -(-(-(-k // 4)) // v) * v
         sn = -(-(-(-n // 4)) // v) * v
-        return e * 45 * (sm * sk + sk * sn)
+        return e * nb * (sm * sk + sk * sn)
     f = sg.strassen_formed_workspace_size_ex
-    assert f(16384, 16384, 16384, 2, sg.STRASSEN_F32, sg.STRASSEN_MODE_BF16X3) == 4 * 90 * 4096 * 4096
+    assert f(16384, 16384, 16384, 2, sg.STRASSEN_F32, sg.STRASSEN_MODE_BF16X3) == 4 * 98 * 4096 * 4096
+    assert f(16384, 16384, 16384, 2, sg.STRASSEN_F32, sg.STRASSEN_MODE_PLAIN) == 4 * 90 * 4096 * 4096
     for (m, n, k) in ((15001, 17003, 9007), (3, 5, 7), (1, 1, 1), (3000, 20000, 5000)):
         assert f(m, n, k, 2, sg.STRASSEN_F32, sg.STRASSEN_MODE_PLAIN) == want(m, n, k, 4, 4)
+        assert f(m, n, k, 2, sg.STRASSEN_F32, sg.STRASSEN_MODE_BF16X3) == want(m, n, k, 4, 4, nb=49)
         assert f(m, n, k, 2, sg.STRASSEN_BF16, sg.STRASSEN_MODE_PLAIN) == want(m, n, k, 2, 8)
         assert f(m, n, k, 1, sg.STRASSEN_F16, sg.STRASSEN_MODE_PLAIN) == \
             sg.strassen_formed_workspace_size(m, n, k, sg.STRASSEN_F16, sg.STRASSEN_MODE_PLAIN)

@@ -279,7 +279,9 @@ def test_formed2_workspace_and_errors():
     sm, sk, sn = 250, 176, 232   # ceil(/4), k and n rounded up to 8 (16-bit) elements
     assert sg.api.formed_workspace_bytes(m, n, k, torch.bfloat16, "plain", levels=2) == 2 * 45 * (sm * sk + sk * sn)
     sm, sk, sn = 250, 176, 228   # fp32: rounded up to 4
-    assert sg.api.formed_workspace_bytes(m, n, k, torch.float32, "bf16x3", levels=2) == 4 * 45 * (sm * sk + sk * sn)
+    # compensated: the single blocks are stored (pre-split) too
+    assert sg.api.formed_workspace_bytes(m, n, k, torch.float32, "bf16x3", levels=2) == 4 * 49 * (sm * sk + sk * sn)
+    assert sg.api.formed_workspace_bytes(m, n, k, torch.float32, "plain", levels=2) == 4 * 45 * (sm * sk + sk * sn)
     prob = make_problem(96, 80, 72, kind="uniform", c_kind="uniform")
     dev = to_device(prob)
     A, B, C = dev["A"], dev["B"], dev["C"]
