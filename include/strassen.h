@@ -234,7 +234,8 @@ int64_t strassen_formed_workspace_size_ex(int64_t m, int64_t n, int64_t k, int l
  * indices as there, hip_stream=15).  A call whose
  * strassen_formed_workspace_size exceeds the scratch returns
  * STRASSEN_ERROR_SCRATCH_LIMIT without launching anything (fp32 data up to
- * about m = n = k = 5180, 16-bit data up to about 7320).  All calls on one
+ * about m = n = k = 5180, 4730 in the BF16X3 mode, 16-bit data up to about
+ * 7320).  All calls on one
  * GPU share that GPU's scratch: calls that overlap in time on one GPU (from
  * several streams or threads) race.  Nothing needs clearing between calls:
  * every scratch element a call reads was written earlier in that call.  The

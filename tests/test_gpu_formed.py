@@ -205,6 +205,73 @@ def test_formed_full_size_bf16x3_equals_fused(size):
     assert en <= tau(1)
 
 
+def _bf16_rne_bits(x):
+    """bf16 bits of fp32 values x rounded to nearest even (finite x)."""
+    u = x.astype(np.float32).view(np.uint32).astype(np.uint64)
+    return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint32) & 0xFFFF
+
+
+def _pre_split_words(s):
+    """The compensated mode's pre-split layout of fp32 values s (rows x
+    cols, cols a multiple of 4): per unit of four elements the words
+    (hi0 | hi1 << 16, hi2 | hi3 << 16, lo0 | lo1 << 16, lo2 | lo3 << 16), hi
+    = bf16(s) and lo = bf16(s - hi), both rounded to nearest even."""
+    hi = _bf16_rne_bits(s)
+    lo = _bf16_rne_bits(s - (hi << 16).view(np.float32))
+    r, c = s.shape
+    hi = hi.reshape(r, c // 4, 2, 2)
+    lo = lo.reshape(r, c // 4, 2, 2)
+    w = np.concatenate([hi[..., 0] | (hi[..., 1] << 16), lo[..., 0] | (lo[..., 1] << 16)], axis=2)
+    return w.reshape(r, c).astype(np.uint32)
+
+
+@pytest.mark.parametrize("m,n,k", [(64, 64, 64), (70, 66, 62)])
+def test_formed_bf16x3_workspace_holds_pre_split_operands(m, n, k):
+    """One level, bf16x3: the workspace holds A's seven operands (five sums,
+    the two single quadrants) and B's five sums, each stored pre-split: the
+    fp32 sum of the stored quadrants with the first term's sign factored
+    out, zero outside the operands' extents, split into bf16 hi and lo
+    halves of each 16-byte unit."""
+    prob = make_problem(m, n, k, kind="uniform", dtype="bf16x3", c_kind="uniform")
+    dev = to_device(prob)
+    need = sg.api.formed_workspace_bytes(m, n, k, torch.float32, "bf16x3")
+    ws = torch.zeros(need, dtype=torch.uint8, device="cuda")
+    _formed(dev, 1.0, 1.0, "bf16x3", ws=ws)
+    words = ws.cpu().numpy().view(np.uint32)
+    sm, sk, sn = -(-m // 2), -(-(-(-k // 2)) // 4) * 4, -(-(-(-n // 2)) // 4) * 4
+    assert need == 4 * (7 * sm * sk + 5 * sk * sn)
+
+    def quadrant(X, rows, cols, q):
+        R, Cc = q // 2, q % 2
+        out = np.zeros((rows, cols), np.float32)
+        blk = X[R * rows:(R + 1) * rows, Cc * cols:(Cc + 1) * cols]
+        out[:blk.shape[0], :blk.shape[1]] = blk
+        return out
+
+    rc, ins = sg.strassen_plan_instances(1)
+    assert rc >= 0
+    A = prob["A"].float().numpy()
+    B = prob["B"].float().numpy()
+    want_a, want_b = [], []
+    for p in ins:
+        for X, rows, cols, nt, blocks, signs, want, single in (
+                (A, sm, sk, p.n_a, p.a_block, p.a_sign, want_a, True),
+                (B, sk, sn, p.n_b, p.b_block, p.b_sign, want_b, False)):
+            if nt == 1 and not single:
+                continue
+            s = quadrant(X, rows, cols, blocks[0])
+            if nt == 2:
+                s = (s + np.float32(signs[1] * signs[0]) * quadrant(X, rows, cols, blocks[1])).astype(np.float32)
+            want.append(_pre_split_words(s))
+    assert len(want_a) == 7 and len(want_b) == 5
+    got_a = words[:7 * sm * sk].reshape(7, sm, sk)
+    got_b = words[7 * sm * sk:].reshape(5, sk, sn)
+    for got, want in ((got_a, want_a), (got_b, want_b)):
+        # every stored block is one of the operands, each operand stored once
+        matched = sorted(next(i for i, w in enumerate(want) if np.array_equal(g, w)) for g in got)
+        assert matched == list(range(len(want)))
+
+
 def test_formed_workspace_errors_on_device():
     prob = make_problem(96, 80, 72, kind="uniform", c_kind="uniform")
     dev = to_device(prob)
