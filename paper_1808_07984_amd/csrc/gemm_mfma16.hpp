@@ -196,6 +196,16 @@ struct Stage {
 // Loads NV consecutive elements of a block starting at (line, run), zero
 // outside lines x runs.  fast: the whole run is inside and aligned.  Lanes
 // whose elements are outside never access memory.
+// Waits until at most N vector-memory loads of this wave are in flight
+// (expcnt and lgkmcnt are left alone).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+
 // PRE: a pre-split operand (whole 16-byte units only: a unit that crosses the
 // extent is loaded whole and its hi and lo halves of the elements outside are
 // cleared).
@@ -726,6 +736,118 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
 
     const int nk = (args.sk + C::KT - 1) / C::KT;
     int kt = 0;
+
+    // Single-term 16-bit products with A and B as stored on 256x256 tiles of
+    // 64-deep k-tiles: the in-bounds k-tiles [0, nfast) are loaded straight
+    // into LDS by the load unit (16-byte global_load_lds, no staging
+    // registers, no LDS stores), two tiles in flight in the two halves of
+    // the LDS buffers, one barrier per tile.  Both tiles are kept as stored
+    // and unpadded: A [m][k] (128-byte rows) and B [k][n] (512-byte rows),
+    // their 16-byte units XOR-swizzled by row ((row / 2) mod 8 for A,
+    // 4 (k mod 4) for B) so that a fragment read cycle hits distinct banks;
+    // each lane's load address picks the unit that lands at its LDS slot.
+    // B's fragments (8 consecutive k of one column) come from two 16-bit
+    // transpose reads (ds_read_b64_tr_b16: within each 16 lanes, lane s
+    // reads 4 consecutive n of k row s/4, and lane L receives column L of
+    // the four rows).  Same MFMAs on the same values in the same order as
+    // the staged loop, so results are bit-identical; the remaining k-tiles
+    // (a ragged end) take the staged loop.  The loads are issued in inline
+    // assembly so that the compiler does not hold every LDS read behind
+    // them; the loop's own vmcnt wait and barrier order them.
+    constexpr bool kDirect = !Ops::kX3 && WA == 1 && WB == 1 && A_KC && !B_KC && C::MT == 256 &&
+                             C::NT == 256 && C::KT == 64 && C::WAVES_M == 2 && C::WAVES_N == 4;
+    if constexpr (kDirect) {
+        static_assert(SA::SIZE * 2 >= 256 * 64 * 2 && SB::SIZE * 2 >= 64 * 256 * 2, "direct tiles fit the buffers");
+        if (nfast >= 1) {
+            const int wv = __builtin_amdgcn_readfirstlane(wave);
+            const int g16 = lane >> 4, s16 = lane & 15;
+            const In *Ab = A + P.a[0].off + a_org;
+            const In *Bb = B + P.b[0].off + b_org;
+            // load slots: instruction i of wave wv fills 1 KB of each tile,
+            // A rows 8 (4 wv + i) .. + 7, B k rows 2 (4 wv + i) and + 1
+            const In *a_src[4];
+            const In *b_src[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 8 * (4 * wv + i) + lane / 8;
+                a_src[i] = Ab + (int64_t)r * lda + 8 * ((lane % 8) ^ ((r >> 1) & 7));
+                const int kr = 2 * (4 * wv + i) + lane / 32;
+                b_src[i] = Bb + (int64_t)kr * ldb + 8 * ((lane % 32) ^ (4 * (kr & 3)));
+            }
+            const uint32_t lds_a[2] = {(uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned short *)&As[0][0][0],
+                                       (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned short *)&As[1][0][0]};
+            const uint32_t lds_b[2] = {(uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned short *)&Bs[0][0][0],
+                                       (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned short *)&Bs[1][0][0]};
+            auto dma = [&](const In *g, uint32_t lds) __attribute__((always_inline)) {
+                asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off"
+                             :: "s"(lds), "v"(g) : "memory", "m0");
+            };
+            auto issue = [&](int t) __attribute__((always_inline)) {
+                const int b = t & 1;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) dma(a_src[i] + (int64_t)t * 64, lds_a[b] + (4 * wv + i) * 1024);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) dma(b_src[i] + (int64_t)t * 64 * ldb, lds_b[b] + (4 * wv + i) * 1024);
+            };
+            // fragment byte offsets within a tile
+            int a_rd[C::BM][4], b_rd[C::BN][4][2];
+#pragma unroll
+            for (int i = 0; i < C::BM; ++i)
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    const int r = wm * C::WM + i * 32 + l32;
+                    a_rd[i][st] = r * 128 + 16 * ((2 * st + h) ^ ((r >> 1) & 7));
+                }
+#pragma unroll
+            for (int j = 0; j < C::BN; ++j)
+#pragma unroll
+                for (int st = 0; st < 4; ++st)
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const int kr = 16 * st + 8 * h + 4 * q + s16 / 4;
+                        const int nc = wn * C::WN + j * 32 + 16 * (g16 & 1) + 4 * (s16 % 4);
+                        b_rd[j][st][q] = kr * 512 + 16 * ((nc / 8) ^ (4 * (kr & 3))) + 2 * (nc % 8);
+                    }
+            issue(0);
+            for (int t = 0; t < nfast; ++t) {
+                wait_vmcnt<0>();
+                __builtin_amdgcn_sched_barrier(0);
+                asm volatile("s_barrier" ::: "memory");
+                __builtin_amdgcn_sched_barrier(0);
+                if (t + 1 < nfast) issue(t + 1);
+                const unsigned char *ta = reinterpret_cast<const unsigned char *>(&As[t & 1][0][0]);
+                const unsigned char *tb = reinterpret_cast<const unsigned char *>(&Bs[t & 1][0][0]);
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    u32x4 af[C::BM], bf[C::BN];
+#pragma unroll
+                    for (int i = 0; i < C::BM; ++i) af[i] = *reinterpret_cast<const u32x4 *>(ta + a_rd[i][st]);
+#pragma unroll
+                    for (int j = 0; j < C::BN; ++j) {
+                        typedef __attribute__((address_space(3))) i16x4 lds_i16x4;
+                        const i16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+                            (lds_i16x4 *)(__attribute__((address_space(3))) const unsigned char *)(tb + b_rd[j][st][0]));
+                        const i16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+                            (lds_i16x4 *)(__attribute__((address_space(3))) const unsigned char *)(tb + b_rd[j][st][1]));
+                        const u32x2 l2 = __builtin_bit_cast(u32x2, lo), h2 = __builtin_bit_cast(u32x2, hi);
+                        bf[j] = u32x4{l2.x, l2.y, h2.x, h2.y};
+                    }
+#pragma unroll
+                    for (int i = 0; i < C::BM; ++i)
+#pragma unroll
+                        for (int j = 0; j < C::BN; ++j) acc[i][j] = mfma(af[i], bf[j], acc[i][j]);
+                }
+            }
+            kt = nfast;
+            if (kt < nk) {
+                // the ragged end: staged loop, tile kt in buffer kt & 1
+                __syncthreads();
+                stage_load(kt * C::KT);
+                stage_store(kt & 1);
+                __syncthreads();
+            }
+        }
+    }
     bool a_pairs_done = false;
     if constexpr (kPairA) {
         if (nfast >= 3) {
@@ -876,7 +998,7 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
         stage_store_from(1, raw_a, raw_b);
         __syncthreads();
         kt += 1;
-    } else {
+    } else if (!(kDirect && nfast >= 1)) {
         if (nfast > 0)
             stage_load_fast(0);
         else
