@@ -737,77 +737,102 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
     const int nk = (args.sk + C::KT - 1) / C::KT;
     int kt = 0;
 
-    // Single-term 16-bit products with A and B as stored on 256x256 tiles of
-    // 64-deep k-tiles: the in-bounds k-tiles [0, nfast) are loaded straight
-    // into LDS by the load unit (16-byte global_load_lds, no staging
-    // registers, no LDS stores), two tiles in flight in the two halves of
-    // the LDS buffers, one barrier per tile.  Both tiles are kept as stored
-    // and unpadded: A [m][k] (128-byte rows) and B [k][n] (512-byte rows),
-    // their 16-byte units XOR-swizzled by row ((row / 2) mod 8 for A,
-    // 4 (k mod 4) for B) so that a fragment read cycle hits distinct banks;
-    // each lane's load address picks the unit that lands at its LDS slot.
-    // B's fragments (8 consecutive k of one column) come from two 16-bit
-    // transpose reads (ds_read_b64_tr_b16: within each 16 lanes, lane s
-    // reads 4 consecutive n of k row s/4, and lane L receives column L of
-    // the four rows).  Same MFMAs on the same values in the same order as
-    // the staged loop, so results are bit-identical; the remaining k-tiles
-    // (a ragged end) take the staged loop.  The loads are issued in inline
-    // assembly so that the compiler does not hold every LDS read behind
-    // them; the loop's own vmcnt wait and barrier order them.
-    constexpr bool kDirect = !Ops::kX3 && WA == 1 && WB == 1 && A_KC && !B_KC && C::MT == 256 &&
-                             C::NT == 256 && C::KT == 64 && C::WAVES_M == 2 && C::WAVES_N == 4;
+    // Single-term products with A and B as stored on 256x256 tiles -- 16-bit
+    // operands on 64-deep k-tiles, and pre-split compensated operands (both
+    // pre-split) on 32-deep ones: the in-bounds k-tiles [0, nfast) are loaded
+    // straight into LDS by the load unit (16-byte global_load_lds, no staging
+    // registers, no LDS stores), two tiles in flight in the two LDS buffers,
+    // one barrier per tile.  Both tiles are kept as stored and unpadded: A
+    // [m][k] (128-byte rows) and B [k][n] (512-byte rows of 16-bit data,
+    // 1024-byte rows of pre-split units), their 16-byte units XOR-swizzled by
+    // row ((row / 2) mod 8 for A, 4 (k mod 4) for B) so that a fragment read
+    // cycle hits distinct banks; each lane's load address picks the unit that
+    // lands at its LDS slot.  B's fragments (8 consecutive k of one column)
+    // come from two 16-bit transpose reads (ds_read_b64_tr_b16: within each
+    // 16 lanes, lane s reads 4 consecutive n of k row s/4, and lane L
+    // receives column L of those four rows), per plane for pre-split data
+    // (the hi and lo halves of each unit).  Same MFMAs on the same values in
+    // the same order as the staged loop, so results are bit-identical; the
+    // remaining k-tiles (a ragged end) take the staged loop.  The loads are
+    // issued in inline assembly so that the compiler does not hold every LDS
+    // read behind them; the loop's own vmcnt wait and barrier order them.
+    constexpr bool kDirect16 = !Ops::kX3 && WA == 1 && WB == 1 && A_KC && !B_KC && C::MT == 256 &&
+                               C::NT == 256 && C::KT == 64 && C::WAVES_M == 2 && C::WAVES_N == 4;
+    constexpr bool kDirectPre = Ops::kPreA && Ops::kPreB && WA == 1 && WB == 1 && A_KC && !B_KC &&
+                                C::MT == 256 && C::NT == 256 && C::KT == 32 && C::WAVES_M == 2 &&
+                                C::WAVES_N == 4;
+    constexpr bool kDirect = kDirect16 || kDirectPre;
     if constexpr (kDirect) {
-        static_assert(SA::SIZE * 2 >= 256 * 64 * 2 && SB::SIZE * 2 >= 64 * 256 * 2, "direct tiles fit the buffers");
+        constexpr int EPU = 16 / (int)sizeof(In);  // elements per 16-byte unit
+        constexpr int BRB = 256 * (int)sizeof(In);  // bytes per B k row
+        constexpr int BRI = 1024 / BRB;             // B k rows per 1 KB load instruction
+        constexpr int BUR = BRB / 16;               // units per B k row
+        constexpr int NST = C::KT / 16;             // MFMA steps per k-tile
+        static_assert(C::KT * (int)sizeof(In) == 128, "128-byte A rows");
+        static_assert((int)sizeof(As[0]) >= 256 * 128 && (int)sizeof(Bs[0]) >= C::KT * BRB,
+                      "direct tiles fit the buffers");
         if (nfast >= 1) {
             const int wv = __builtin_amdgcn_readfirstlane(wave);
             const int g16 = lane >> 4, s16 = lane & 15;
-            const In *Ab = A + P.a[0].off + a_org;
-            const In *Bb = B + P.b[0].off + b_org;
+            const char *Ab = reinterpret_cast<const char *>(A + P.a[0].off + a_org);
+            const char *Bb = reinterpret_cast<const char *>(B + P.b[0].off + b_org);
             // load slots: instruction i of wave wv fills 1 KB of each tile,
-            // A rows 8 (4 wv + i) .. + 7, B k rows 2 (4 wv + i) and + 1
-            const In *a_src[4];
-            const In *b_src[4];
+            // A rows 8 (4 wv + i) .. + 7, B k rows BRI (4 wv + i) ..; each
+            // lane's byte offset from the tile's base (below 2^32: nfast
+            // requires it)
+            uint32_t a_ld[4], b_ld[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int r = 8 * (4 * wv + i) + lane / 8;
-                a_src[i] = Ab + (int64_t)r * lda + 8 * ((lane % 8) ^ ((r >> 1) & 7));
-                const int kr = 2 * (4 * wv + i) + lane / 32;
-                b_src[i] = Bb + (int64_t)kr * ldb + 8 * ((lane % 32) ^ (4 * (kr & 3)));
+                a_ld[i] = (uint32_t)sizeof(In) * ((uint32_t)r * (uint32_t)lda + EPU * ((lane % 8) ^ ((r >> 1) & 7)));
+                const int kr = BRI * (4 * wv + i) + lane / BUR;
+                b_ld[i] = (uint32_t)sizeof(In) * ((uint32_t)kr * (uint32_t)ldb + EPU * ((lane % BUR) ^ (4 * (kr & 3))));
             }
             const uint32_t lds_a[2] = {(uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned short *)&As[0][0][0],
                                        (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned short *)&As[1][0][0]};
             const uint32_t lds_b[2] = {(uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned short *)&Bs[0][0][0],
                                        (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned short *)&Bs[1][0][0]};
-            auto dma = [&](const In *g, uint32_t lds) __attribute__((always_inline)) {
-                asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off"
-                             :: "s"(lds), "v"(g) : "memory", "m0");
+            // 16 bytes per lane from base + off into LDS at lds + 16 lane
+            auto dma = [&](const char *base, uint32_t off, uint32_t lds) __attribute__((always_inline)) {
+                asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, %2"
+                             :: "s"(lds), "v"(off), "s"(base) : "memory", "m0");
             };
             auto issue = [&](int t) __attribute__((always_inline)) {
                 const int b = t & 1;
+                const char *at = Ab + (int64_t)t * C::KT * (int64_t)sizeof(In);
+                const char *bt = Bb + (int64_t)t * C::KT * ldb * (int64_t)sizeof(In);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) dma(a_src[i] + (int64_t)t * 64, lds_a[b] + (4 * wv + i) * 1024);
+                for (int i = 0; i < 4; ++i) dma(at, a_ld[i], lds_a[b] + (4 * wv + i) * 1024);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) dma(b_src[i] + (int64_t)t * 64 * ldb, lds_b[b] + (4 * wv + i) * 1024);
+                for (int i = 0; i < 4; ++i) dma(bt, b_ld[i], lds_b[b] + (4 * wv + i) * 1024);
             };
-            // fragment byte offsets within a tile
-            int a_rd[C::BM][4], b_rd[C::BN][4][2];
+            // fragment byte offsets within a tile.  A: row ra + 32 i, 16-byte
+            // unit (2 st + h) of 16-bit data or (4 st + 2 h + u) of pre-split
+            // data; rows 32 apart share the swizzle, so i adds 4096 bytes.
+            // B: k row kr0 + 16 st + 4 q (kr mod 4 = s16 / 4 for every st, q),
+            // column block nc of fragment j.
+            constexpr int AU = kDirectPre ? 2 : 1;
+            const int ra = wm * C::WM + l32;
+            int a_rd[NST][AU], b_rd[C::BN];
 #pragma unroll
-            for (int i = 0; i < C::BM; ++i)
+            for (int st = 0; st < NST; ++st)
 #pragma unroll
-                for (int st = 0; st < 4; ++st) {
-                    const int r = wm * C::WM + i * 32 + l32;
-                    a_rd[i][st] = r * 128 + 16 * ((2 * st + h) ^ ((r >> 1) & 7));
+                for (int u = 0; u < AU; ++u) {
+                    const int unit = kDirectPre ? 4 * st + 2 * h + u : 2 * st + h;
+                    a_rd[st][u] = ra * 128 + 16 * (unit ^ ((ra >> 1) & 7));
                 }
+            const int kr0 = 8 * h + s16 / 4;
 #pragma unroll
-            for (int j = 0; j < C::BN; ++j)
-#pragma unroll
-                for (int st = 0; st < 4; ++st)
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) {
-                        const int kr = 16 * st + 8 * h + 4 * q + s16 / 4;
-                        const int nc = wn * C::WN + j * 32 + 16 * (g16 & 1) + 4 * (s16 % 4);
-                        b_rd[j][st][q] = kr * 512 + 16 * ((nc / 8) ^ (4 * (kr & 3))) + 2 * (nc % 8);
-                    }
+            for (int j = 0; j < C::BN; ++j) {
+                const int nc = wn * C::WN + j * 32 + 16 * (g16 & 1) + 4 * (s16 % 4);
+                b_rd[j] = kr0 * BRB + 16 * ((nc / EPU) ^ (4 * (s16 / 4))) + 2 * (nc % EPU);
+            }
+            typedef __attribute__((address_space(3))) i16x4 lds_i16x4;
+            auto tr = [&](const unsigned char *p) __attribute__((always_inline)) -> u32x2 {
+                return __builtin_bit_cast(
+                    u32x2, __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+                               (lds_i16x4 *)(__attribute__((address_space(3))) const unsigned char *)p));
+            };
             issue(0);
             for (int t = 0; t < nfast; ++t) {
                 wait_vmcnt<0>();
@@ -818,24 +843,37 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
                 const unsigned char *ta = reinterpret_cast<const unsigned char *>(&As[t & 1][0][0]);
                 const unsigned char *tb = reinterpret_cast<const unsigned char *>(&Bs[t & 1][0][0]);
 #pragma unroll
-                for (int st = 0; st < 4; ++st) {
-                    u32x4 af[C::BM], bf[C::BN];
+                for (int st = 0; st < NST; ++st) {
+                    u32x4 af[NPLANES][C::BM], bf[NPLANES][C::BN];
 #pragma unroll
-                    for (int i = 0; i < C::BM; ++i) af[i] = *reinterpret_cast<const u32x4 *>(ta + a_rd[i][st]);
-#pragma unroll
-                    for (int j = 0; j < C::BN; ++j) {
-                        typedef __attribute__((address_space(3))) i16x4 lds_i16x4;
-                        const i16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
-                            (lds_i16x4 *)(__attribute__((address_space(3))) const unsigned char *)(tb + b_rd[j][st][0]));
-                        const i16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
-                            (lds_i16x4 *)(__attribute__((address_space(3))) const unsigned char *)(tb + b_rd[j][st][1]));
-                        const u32x2 l2 = __builtin_bit_cast(u32x2, lo), h2 = __builtin_bit_cast(u32x2, hi);
-                        bf[j] = u32x4{l2.x, l2.y, h2.x, h2.y};
+                    for (int i = 0; i < C::BM; ++i) {
+                        if constexpr (kDirectPre) {
+                            const u32x4 u0 = *reinterpret_cast<const u32x4 *>(ta + a_rd[st][0] + 4096 * i);
+                            const u32x4 u1 = *reinterpret_cast<const u32x4 *>(ta + a_rd[st][1] + 4096 * i);
+                            af[0][i] = u32x4{u0[0], u0[1], u1[0], u1[1]};
+                            af[NPLANES - 1][i] = u32x4{u0[2], u0[3], u1[2], u1[3]};
+                        } else {
+                            af[0][i] = *reinterpret_cast<const u32x4 *>(ta + a_rd[st][0] + 4096 * i);
+                        }
                     }
+#pragma unroll
+                    for (int j = 0; j < C::BN; ++j)
+#pragma unroll
+                        for (int q = 0; q < NPLANES; ++q) {  // plane q: the unit's half at byte 8 q
+                            const unsigned char *pb = tb + b_rd[j] + 16 * st * BRB + 8 * q;
+                            const u32x2 l2 = tr(pb), h2 = tr(pb + 4 * BRB);
+                            bf[q][j] = u32x4{l2.x, l2.y, h2.x, h2.y};
+                        }
 #pragma unroll
                     for (int i = 0; i < C::BM; ++i)
 #pragma unroll
-                        for (int j = 0; j < C::BN; ++j) acc[i][j] = mfma(af[i], bf[j], acc[i][j]);
+                        for (int j = 0; j < C::BN; ++j) {
+                            acc[i][j] = mfma(af[0][i], bf[0][j], acc[i][j]);
+                            if constexpr (Ops::kX3) {
+                                acc[i][j] = mfma(af[0][i], bf[NPLANES - 1][j], acc[i][j]);
+                                acc[i][j] = mfma(af[NPLANES - 1][i], bf[0][j], acc[i][j]);
+                            }
+                        }
                 }
             }
             kt = nfast;
