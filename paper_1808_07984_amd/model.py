@@ -32,7 +32,12 @@ measured on MI355X:
 
 R_A, R_B, R_C, T_round and the 0.85 factor of the 128 x 128 tile's operand
 rates are fitted to the event times of every launch of squares 1024-16384 at
-levels 0/1/2 (fp32, bf16 and the compensated mode, fused and formed).  They are per-CU rates
+levels 0/1/2 (fp32, bf16 and the compensated mode, fused and formed).
+Launches that load their operands straight into LDS (the single-term
+products on 256 x 256 tiles, 16-bit or pre-split compensated) have no
+staging lane-ops of their own (16-bit) or DIRECT_VALU of the staged split's
+(pre-split: 0.4, fitted to the same table); their operand rates are those of
+the staged loads.  They are per-CU rates
 of latency-bound loads, not bandwidths: the sixteen-bit kernels reach about
 a third of their MFMA peak on the plain product, and their multi-term launches
 are set by how many operand bytes a CU can keep in flight.  The B operand
@@ -65,6 +70,10 @@ R_A_B_PER_S_CU = 58e9        # A-operand bytes per second per CU (fitted)
 R_B_B_PER_S_CU = 29e9        # B-operand bytes per second per CU (fitted)
 R_C_B_PER_S_CU = 26e9        # epilogue C bytes per second per CU (fitted)
 SMALL_TILE_FETCH = 0.85      # 128x128 tile: operand time factor (fitted)
+# operands loaded straight into LDS: factor on the staging lane-ops (none for
+# 16-bit data; for pre-split compensated data, fitted: the units' hi and lo
+# halves are still regrouped per fragment)
+DIRECT_VALU = {"16bit": 0.0, "x3": 0.4}
 ROUND_S = 7e-6               # fixed cost per round of workgroups (fitted)
 FORM_B_PER_S = 5.0e12        # sum-forming kernels, bytes read + written (measured)
 HBM_B_PER_S = 8.0e12
@@ -99,11 +108,22 @@ def _staging(kind, w):
     return 0.125 if w == 1 else 2.0 * w + 0.5
 
 
-def launch(kind, large, wa, wb, wc, sm, sn, sk, batch, products_per_workgroup=1):
+def direct_loads(kind, large, wa, wb, pre_b=True):
+    """Whether the library loads this variant's in-bounds k-tiles straight
+    into LDS: single-term products with A and B as stored on 256x256 tiles,
+    16-bit operands or pre-split compensated ones (pre_b: B pre-split too,
+    as in the formed schedules except for the one-level products that read B
+    as stored)."""
+    return large and wa == 1 and wb == 1 and (kind == "16bit" or (kind == "x3" and pre_b))
+
+
+def launch(kind, large, wa, wb, wc, sm, sn, sk, batch, products_per_workgroup=1, direct=False):
     """Predicted seconds of one launch: `batch` products of sm x sk by
     sk x sn sub-blocks with W_A, W_B, W_C terms, each workgroup running
     `products_per_workgroup` products in turn (2 for a chained launch) and
-    one epilogue of wc outputs.  Returns a dict of the terms."""
+    one epilogue of wc outputs; direct: the operands go straight into LDS
+    (staging lane-ops scaled by DIRECT_VALU).  Returns a dict of the
+    terms."""
     mt, nt, kt = tile(kind, large, wa, wb, wc)
     b_in = 2 if kind == "16bit" else 4
     b_lds = 4 if kind == "f32" else 2
@@ -116,8 +136,8 @@ def launch(kind, large, wa, wb, wc, sm, sn, sk, batch, products_per_workgroup=1)
     ktiles = math.ceil(sk / kt) * products_per_workgroup
     per_wg = {
         "flop": 2.0 * mt * nt * kt * ktiles * mult / (rate * clock),
-        "valu": (mt * _staging(kind, wa) + nt * _staging(kind, wb)) * kt * ktiles
-                / (VALU_OPS_PER_CLK_CU * clock),
+        "valu": (DIRECT_VALU.get(kind, 1.0) if direct else 1.0)
+                * (mt * _staging(kind, wa) + nt * _staging(kind, wb)) * kt * ktiles / (VALU_OPS_PER_CLK_CU * clock),
         "lds": ((mt + nt) * kt * b_lds * planes / LDS_WRITE_B_PER_CLK_CU
                 + waves * (wm + wn) * kt * b_lds * planes / LDS_READ_B_PER_CLK_CU) * ktiles / clock,
         "fetch": (wa * mt / R_A_B_PER_S_CU + wb * nt / R_B_B_PER_S_CU) * kt * b_in * ktiles
@@ -200,7 +220,8 @@ def predict(m, n, k, levels, kind="f32"):
     launches = []
     for wa, wb, wc, batch in _batches(levels):
         large = _use_large(sm, sn, sk, batch, kind == "f32")
-        launches.append(launch(kind, large, wa, wb, wc, sm, sn, sk, batch))
+        launches.append(launch(kind, large, wa, wb, wc, sm, sn, sk, batch,
+                               direct=kind == "16bit" and direct_loads(kind, large, wa, wb)))
     return sum(l["seconds"] for l in launches), launches
 
 
@@ -229,21 +250,30 @@ def predict_formed(m, n, k, levels, kind="f32"):
     launches = []
     for wa, wb, wc, batch in _batches(levels):
         large = _use_large(sm, sn, sk, batch, kind == "f32")
-        launches.append(launch(kind, large, 1, 1, wc, sm, sn, sk, batch))
+        # compensated one level: the batch whose B operands are single
+        # quadrants reads them as stored (fp32, split while staged)
+        pre_b = levels == 2 or wb > 1
+        launches.append(launch(kind, large, 1, 1, wc, sm, sn, sk, batch,
+                               direct=direct_loads(kind, large, 1, 1, pre_b)))
     return sum(forms) + sum(l["seconds"] for l in launches), forms + launches
 
 
 def parse_kernel(name):
-    """(kind, large, (W_A, W_B, W_C) or None, chains or 0) from a launch
-    record's kernel name; kind None for the sum-forming kernels."""
+    """(kind, large, (W_A, W_B, W_C) or None, chains or 0, direct) from a
+    launch record's kernel name; kind None for the sum-forming kernels.
+    direct: the variant loads its operands straight into LDS (16-bit and
+    pre-split compensated single-term products as stored, 256x256 tiles)."""
     if name.startswith("form_"):
-        return None, False, None, 0
+        return None, False, None, 0, False
     kind = "f32" if name.startswith("strassen_f32") else "x3" if "bf16x3" in name else "16bit"
     large = "256x256" in name
+    pre_b = "bf16x3p," in name
     args = name[name.rindex("<") + 1:name.rindex(">")].split(",")
+    untransposed = "tA" not in args and "tB" not in args
     if args[0] == "chained":
-        return kind, large, None, int(args[1])
-    return kind, large, tuple(int(v) for v in args[:3]), 0
+        return kind, large, None, int(args[1]), direct_loads(kind, large, 1, 1, pre_b)
+    w = tuple(int(v) for v in args[:3])
+    return kind, large, w, 0, untransposed and direct_loads(kind, large, w[0], w[1], pre_b)
 
 
 def predict_record(kernel, batch, workgroups, sm, sn, sk, kind_hint=None):
@@ -252,12 +282,12 @@ def predict_record(kernel, batch, workgroups, sm, sn, sk, kind_hint=None):
     Sum-forming launches: one level, one operand's four quadrants into five
     sums of sm x sk; two levels (form_terms), `workgroups` distinct blocks
     into `batch` sums (kind_hint gives their element type)."""
-    kind, large, variant, chains = parse_kernel(kernel)
+    kind, large, variant, chains, direct = parse_kernel(kernel)
     if kind is None:
         fk = "16bit" if "16-bit" in kernel else "x3"
         if kernel.startswith("form_terms"):
             return form(kind_hint or fk, sm, sk, workgroups, batch)
         return form(kind_hint or fk, sm, sk, 4, batch)
     if chains:
-        return launch(kind, large, 1, 1, 2, sm, sn, sk, chains, products_per_workgroup=2)["seconds"]
-    return launch(kind, large, *variant, sm, sn, sk, batch)["seconds"]
+        return launch(kind, large, 1, 1, 2, sm, sn, sk, chains, products_per_workgroup=2, direct=direct)["seconds"]
+    return launch(kind, large, *variant, sm, sn, sk, batch, direct=direct)["seconds"]

@@ -162,13 +162,15 @@ def _launch_prediction(r):
     m = re.match(r"form \((\d+) > (\d+)\)$", tok)
     if m:
         return model.form(kind if kind != "f32" else "x3", s, s, int(m.group(1)), int(m.group(2)))
+    direct = tok.endswith(" direct")
+    tok = tok[:-len(" direct")] if direct else tok
     m = re.match(r"(\d+) chained (\d+)$", tok)
     if m:
         return model.launch(kind, m.group(1) == "256", 1, 1, 2, s, s, s, int(m.group(2)),
-                            products_per_workgroup=2)["seconds"]
+                            products_per_workgroup=2, direct=direct)["seconds"]
     m = re.match(r"(\d+) \((\d),(\d),(\d)\)$", tok)
     wa, wb, wc = (int(v) for v in m.group(2, 3, 4))
-    return model.launch(kind, m.group(1) == "256", wa, wb, wc, s, s, s, int(r["batch"]))["seconds"]
+    return model.launch(kind, m.group(1) == "256", wa, wb, wc, s, s, s, int(r["batch"]), direct=direct)["seconds"]
 
 
 def test_measured_launches_are_predicted():
@@ -210,7 +212,7 @@ def test_measured_launch_workgroups_match_model():
         m = re.match(r"(\d+) ", r["kernel"])
         t = int(m.group(1))
         per = math.ceil(s / t) ** 2
-        chains = re.match(r"\d+ chained (\d+)$", r["kernel"])
+        chains = re.match(r"\d+ chained (\d+)( direct)?$", r["kernel"])
         assert int(r["wg"]) == per * (int(chains.group(1)) if chains else int(r["batch"]))
 
 
