@@ -365,10 +365,13 @@ def precision_section(sizes, steps, dev, stream, log):
 
 def compensated_section(sizes, steps, rounds, dev, stream, log):
     """The compensated bf16x3 mode on fp32 N(0,1) operands, C := A*B (the
-    precision workload) at m=n=k in `sizes`: the plain product, the fused
+    precision workload) at m=n=k in `sizes`: the plain product (as stored,
+    and on pre-split copies of A and B: the formed call at level 0, the
+    operand path of the formed products), the fused
     one-level call, the formed one-level call (two-term sums formed into
-    workspace first, bit-identical to the fused one) and the fused two-level
-    call, timed in `rounds` interleaved rounds of `steps` calls each (the
+    workspace first, bit-identical to the fused one) and the fused and formed
+    two-level calls; the Strassen calls' speedups are against the faster of
+    the two plain products.  Timed in `rounds` interleaved rounds of `steps` calls each (the
     16-bit matrix cores run power-limited, so the variants are timed in
     turn under the same conditions); the median round of each is reported.
     Also: the formed call's form and product launch times (library events),
@@ -385,10 +388,11 @@ def compensated_section(sizes, steps, rounds, dev, stream, log):
         A = inputs.normal(N, N, inputs.SEED_A).to(dev)
         B = inputs.normal(N, N, inputs.SEED_B).to(dev)
         C = torch.zeros(N, N, device=dev)
-        ws = torch.empty(max(sg.api.formed_workspace_bytes(N, N, N, torch.float32, "bf16x3", lv) for lv in (1, 2)),
+        ws = torch.empty(max(sg.api.formed_workspace_bytes(N, N, N, torch.float32, "bf16x3", lv) for lv in (0, 1, 2)),
                          dtype=torch.uint8, device=dev)
         variants = {
             "L0": lambda: sg.gemm(A, B, C, 1.0, 0.0, levels=0, mode="bf16x3"),
+            "L0_formed": lambda: sg.gemm_formed(A, B, C, 1.0, 0.0, mode="bf16x3", workspace=ws, levels=0),
             "L1_fused": lambda: sg.gemm(A, B, C, 1.0, 0.0, levels=1, mode="bf16x3"),
             "L1_formed": lambda: sg.gemm_formed(A, B, C, 1.0, 0.0, mode="bf16x3", workspace=ws),
             "L2_fused": lambda: sg.gemm(A, B, C, 1.0, 0.0, levels=2, mode="bf16x3"),
@@ -400,13 +404,17 @@ def compensated_section(sizes, steps, rounds, dev, stream, log):
         want, _ = sampled_reference(A, B, None, rows, cols, 1.0, 0.0)
         scale = N * float(A.abs().max()) * float(B.abs().max())
         errs = {}
-        ref1 = ref2 = None
+        ref0 = ref1 = ref2 = None
         for name, fn in variants.items():
             fn()
             torch.cuda.synchronize()
             err = float(np.abs(sampled_got(C, rows, cols) - want).max())
             errs[name] = {"e_norm_2m16": round(err / (2.0 ** -16 * scale), 5),
                           "e_norm_2m23": round(err / (2.0 ** -23 * scale), 4)}
+            if name == "L0":
+                ref0 = C.clone()
+            if name == "L0_formed" and not torch.equal(C, ref0):
+                raise SystemExit("pre-split plain result differs from the plain one at N=%d" % N)
             if name == "L1_fused":
                 ref1 = C.clone()
             if name == "L2_fused":
@@ -420,7 +428,7 @@ def compensated_section(sizes, steps, rounds, dev, stream, log):
                 if not (torch.equal(C[:h, h:], ref1[:h, h:]) and torch.equal(C[h:, :h], ref1[h:, :h])
                         and errs[name]["e_norm_2m16"] <= 4.0):
                     raise SystemExit("formed one-level result check failed at N=%d" % N)
-        del ref1, ref2
+        del ref0, ref1, ref2
         times = {name: [] for name in variants}
         for _ in range(rounds):
             for name, fn in variants.items():
@@ -439,13 +447,16 @@ def compensated_section(sizes, steps, rounds, dev, stream, log):
         row["L1_formed"]["form_ms"] = round(forms, 4)
         row["L1_formed"]["product_ms"] = round(prods, 4)
         row["L1_formed"]["workspace_bytes"] = int(ws.numel())
-        row["L1_formed_vs_L0"] = round(row["L0"]["ms_per_step"] / row["L1_formed"]["ms_per_step"], 4)
-        row["L1_fused_vs_L0"] = round(row["L0"]["ms_per_step"] / row["L1_fused"]["ms_per_step"], 4)
-        row["L2_formed_vs_L0"] = round(row["L0"]["ms_per_step"] / row["L2_formed"]["ms_per_step"], 4)
+        # speedups against the faster plain product
+        plain = min(row["L0"]["ms_per_step"], row["L0_formed"]["ms_per_step"])
+        row["plain_ms"] = plain
+        row["L1_formed_vs_L0"] = round(plain / row["L1_formed"]["ms_per_step"], 4)
+        row["L1_fused_vs_L0"] = round(plain / row["L1_fused"]["ms_per_step"], 4)
+        row["L2_formed_vs_L0"] = round(plain / row["L2_formed"]["ms_per_step"], 4)
         out[str(N)] = row
-        log("bf16x3 N=%d (median of %d rounds): L0 %.3f  L1 fused %.3f  L1 formed %.3f (forms %.3f)  "
-            "L2 fused %.3f  L2 formed %.3f ms;  formed speedup over plain %.3fx (L1) %.3fx (L2), fused %.3fx"
-            % (N, rounds, row["L0"]["ms_per_step"], row["L1_fused"]["ms_per_step"],
+        log("bf16x3 N=%d (median of %d rounds): L0 %.3f  L0 pre-split %.3f  L1 fused %.3f  L1 formed %.3f (forms %.3f)  "
+            "L2 fused %.3f  L2 formed %.3f ms;  formed speedup over the faster plain %.3fx (L1) %.3fx (L2), fused %.3fx"
+            % (N, rounds, row["L0"]["ms_per_step"], row["L0_formed"]["ms_per_step"], row["L1_fused"]["ms_per_step"],
                row["L1_formed"]["ms_per_step"], forms, row["L2_fused"]["ms_per_step"],
                row["L2_formed"]["ms_per_step"], row["L1_formed_vs_L0"], row["L2_formed_vs_L0"],
                row["L1_fused_vs_L0"]))

@@ -186,9 +186,14 @@ int strassen_gemm_formed(int64_t m, int64_t n, int64_t k,
 int64_t strassen_formed_workspace_size(int64_t m, int64_t n, int64_t k,
                                        strassen_dtype_t dtype, strassen_mode_t mode);
 
-/* strassen_gemm_formed at one or two levels (levels = 1 or 2; eq.
+/* strassen_gemm_formed at zero, one or two levels (levels = 0, 1 or 2; eq.
  * "gpu_allops" applied twice, the Two-Level Strassen's Algorithm section's
- * 49 products).  At two levels every multi-term operand of the 49 products
+ * 49 products).  Level 0 is the plain product (as strassen_gemm_ex at
+ * levels = 0, bit for bit); in the BF16X3 mode A and B are first written
+ * pre-split into workspace, so the product stages them without splitting
+ * (the plain product with the same operand path as the formed Strassen
+ * products); in the PLAIN mode nothing is formed and no workspace is
+ * needed.  At two levels every multi-term operand of the 49 products
  * (25 four-term and 20 two-term sums of A, the same of B, on the 4 x 4 block
  * grid) is formed once into workspace, one launch per level-1 operand
  * reading its at most eight blocks once, with the fused kernels' arithmetic
@@ -213,8 +218,9 @@ int strassen_gemm_formed_ex(int64_t m, int64_t n, int64_t k,
                             float alpha, float beta, int levels, strassen_mode_t mode,
                             void *workspace, int64_t workspace_bytes, void *hip_stream);
 
-/* Workspace bytes strassen_gemm_formed_ex needs: at one level as
- * strassen_formed_workspace_size; at two levels e * 45 (sm sk + sk sn) with
+/* Workspace bytes strassen_gemm_formed_ex needs: at level 0 none (PLAIN
+ * mode) or 4 (m sk + sk sn) with sk, sn = k, n rounded up to 4 (BF16X3);
+ * at one level as strassen_formed_workspace_size; at two levels e * 45 (sm sk + sk sn) with
  * the two-level block extents sm = ceil(m/4), sk = ceil(k/4), sn = ceil(n/4)
  * (sk, sn rounded up as above), about 2.8 (mk + kn) e bytes; BF16X3 mode
  * 4 * 49 (sm sk + sk sn) (the four single blocks of each operand that

@@ -103,8 +103,9 @@ def formed_workspace_bytes(m, n, k, dtype=torch.float32, mode="plain", levels=1)
 
 def gemm_formed(A, B_, C, alpha=1.0, beta=1.0, mode="plain", workspace=None, stream=None, levels=1):
     """One- or two-level Strassen with the multi-term operand sums formed
-    first into workspace: C := alpha * A @ B + beta * C in place.  Equal to
-    gemm(..., levels=levels) bit for bit, except that at one level on the
+    first into workspace: C := alpha * A @ B + beta * C in place (levels=0:
+    the plain product, on pre-split copies of A and B in the bf16x3 mode).
+    Equal to gemm(..., levels=levels) bit for bit, except that at one level on the
     16-bit matrix cores with 256x256 tiles the products M5 and M6 are
     accumulated after M2 and M3 and added into C3 and C0 with them, so those
     two blocks can differ in the last bits.  A, B: fp32, bf16 or fp16 GPU tensors of one dtype,

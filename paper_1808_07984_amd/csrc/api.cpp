@@ -764,7 +764,8 @@ struct FormedGeom {
     // Compensated mode: the workspace operands are written pre-split, and
     // the single blocks that products take as operands too -- A's at one
     // level (B's single quadrants are read as stored by the products that
-    // run beside B's form), A's and B's at two levels -- so that products
+    // run beside B's form), A's and B's at two levels and at level 0 (the
+    // plain product on pre-split copies of A and B) -- so that products
     // stage pre-split operands.
     bool pre = false;
 };
@@ -787,7 +788,14 @@ FormedGeom formed_geom(int64_t m, int64_t n, int64_t k, const Family &fam, int l
     FormedGeom g;
     g.plan = strassen::make_plan(m, n, k, levels, fam.vec);
     g.pre = fam.m16 && fam.op == strassen::Operand16::kBf16x3;
-    const bool b_singles = g.pre && levels == 2;
+    if (levels == 0 && g.pre) {
+        // pre-split copies need whole 16-byte units per row: the workspace
+        // blocks' k and n extents are rounded up (the product's own extents
+        // clip at k and n; rounding by less than 4 adds no tile)
+        g.plan.sk = (g.plan.sk + fam.vec - 1) / fam.vec * fam.vec;
+        g.plan.sn = (g.plan.sn + fam.vec - 1) / fam.vec * fam.vec;
+    }
+    const bool b_singles = g.pre && levels != 1;
     for (const strassen::Product &p : g.plan.products) {
         g.a_of.push_back(p.na > 1 || g.pre ? find_or_add(g.asums, p.a, p.na) : -1);
         g.b_of.push_back(p.nb > 1 || b_singles ? find_or_add(g.bsums, p.b, p.nb) : -1);
@@ -1417,7 +1425,7 @@ int64_t formed_size(int64_t m, int64_t n, int64_t k, int levels, strassen_dtype_
     if (m < 0 || m >= kMaxDim) return -1;
     if (n < 0 || n >= kMaxDim) return -2;
     if (k < 0 || k >= kMaxDim) return -3;
-    if (levels != 1 && levels != 2) return -4;
+    if (levels < 0 || levels > 2) return -4;
     if (!valid_dtype(dtype)) return -5;
     if (mode != STRASSEN_MODE_PLAIN && mode != STRASSEN_MODE_BF16X3) return -6;
     if (mode == STRASSEN_MODE_BF16X3 && dtype != STRASSEN_F32) return -6;
@@ -1454,12 +1462,13 @@ int formed_call(int64_t m, int64_t n, int64_t k, const void *A, int64_t lda, str
                  alpha, beta, levels, mode, (hipStream_t)hip_stream};
     const int v = validate(c);
     if (v != 0) return to_formed_ex_index(v);
-    if (levels != 1 && levels != 2) return -14;
+    if (levels < 0 || levels > 2) return -14;
     const bool product = m > 0 && n > 0 && k > 0 && alpha != 0.f;
     try {
         if (!product) return run_formed(c, nullptr);
         const int64_t need = formed_size(m, n, k, levels, a_type, mode);
         if (need < 0) return (int)(-need);
+        if (need == 0) return run_formed(c, nullptr);  // level 0 on stored operands: nothing to form
         if (workspace == nullptr || (uintptr_t)workspace % 16 != 0) return -16;
         if (workspace_bytes < need) return -17;
         const uint64_t wbytes = (uint64_t)need;

@@ -195,8 +195,12 @@ def test_formed_workspace_size_two_levels():
             sg.strassen_formed_workspace_size(m, n, k, sg.STRASSEN_F16, sg.STRASSEN_MODE_PLAIN)
     assert f(-1, 1, 1, 2, 0, 0) == -1
     assert f(1, 1, -1, 2, 0, 0) == -3
-    assert f(1, 1, 1, 0, 0, 0) == -4
+    assert f(1, 1, 1, -1, 0, 0) == -4
     assert f(1, 1, 1, 3, 0, 0) == -4
+    # level 0: nothing formed in the PLAIN mode, pre-split copies of A and B in BF16X3
+    assert f(1000, 900, 700, 0, sg.STRASSEN_F32, sg.STRASSEN_MODE_PLAIN) == 0
+    assert f(1000, 900, 700, 0, sg.STRASSEN_BF16, sg.STRASSEN_MODE_PLAIN) == 0
+    assert f(1000, 900, 701, 0, sg.STRASSEN_F32, sg.STRASSEN_MODE_BF16X3) == 4 * (1000 * 704 + 704 * 900)
     assert f(1, 1, 1, 2, 7, 0) == -5
     assert f(1, 1, 1, 2, sg.STRASSEN_BF16, sg.STRASSEN_MODE_BF16X3) == -6
 
@@ -215,7 +219,7 @@ def test_formed_ex_validation():
     assert call(A=None) == -4
     assert call(b_type=1) == -9
     assert call(ldc=3) == -11
-    assert call(levels=0) == -14
+    assert call(levels=-1) == -14
     assert call(levels=3) == -14
     assert call(mode=4) == -15
     assert call(ws=None) == -16

@@ -356,7 +356,7 @@ def test_formed2_workspace_and_errors():
     ws = torch.empty(need + 64, dtype=torch.uint8, device="cuda")
     common = (96, 80, 72, A.data_ptr(), A.stride(0), sg.STRASSEN_F32, B.data_ptr(), B.stride(0), sg.STRASSEN_F32,
               C.data_ptr(), C.stride(0), 1.0, 1.0)
-    for bad in (0, 3):
+    for bad in (-1, 3):
         assert sg.strassen_gemm_formed_ex(*common, bad, sg.STRASSEN_MODE_PLAIN, ws.data_ptr(), need, None) == -14
     assert sg.strassen_gemm_formed_ex(*common, 2, sg.STRASSEN_MODE_PLAIN, ws.data_ptr() + 4, need, None) == -16
     assert sg.strassen_gemm_formed_ex(*common, 2, sg.STRASSEN_MODE_PLAIN, ws.data_ptr(), need - 16, None) == -17
@@ -391,6 +391,40 @@ def test_formed2_full_size_equals_fused(fam):
 def _random_shapes(count, seed):
     rng = np.random.default_rng(seed)
     return [tuple(int(v) for v in rng.integers(1, 700, 3)) for _ in range(count)]
+
+
+@pytest.mark.parametrize("fam", sorted(FAMILIES))
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (65, 67, 63), (257, 130, 301), (1030, 1100, 1503)])
+def test_formed0_equals_plain(fam, m, n, k):
+    """Level 0: the plain product (on pre-split copies of A and B in the
+    bf16x3 mode), bit for bit the plain call's result, alpha and beta
+    applied; integers exact against the oracle."""
+    dtype, mode = FAMILIES[fam]
+    prob = make_problem(m, n, k, kind="uniform", dtype=dtype, c_kind="uniform")
+    d1, d2 = to_device(prob), to_device(prob)
+    got = _formed(d1, 1.25, 0.5, mode, levels=0)
+    sg.gemm(d2["A"], d2["B"], d2["C"], alpha=1.25, beta=0.5, levels=0, mode=mode)
+    torch.cuda.synchronize()
+    assert torch.equal(got, d2["C"])
+    prob = make_problem(m, n, k, kind="integers", dtype=dtype, c_kind="integers")
+    dev = to_device(prob)
+    got = _formed(dev, 1.0, 1.0, mode, levels=0)
+    want = oracle.gemm_f64(prob["A"], prob["B"], prob["C"], 1.0, 1.0)
+    assert np.array_equal(got.cpu().double().numpy(), want)
+
+
+def test_formed0_full_size_bf16x3_equals_plain():
+    """8192^3, bf16x3: the pre-split plain product (direct-to-LDS loads)
+    equals the plain call bit for bit."""
+    n = 8192
+    prob = make_problem(n, n, n, kind="normal", dtype="bf16x3", c_kind="normal", fill=0.0)
+    d1 = to_device(prob)
+    C0 = d1["C"].clone()
+    got = _formed(d1, 1.0, 1.0, "bf16x3", levels=0).clone()
+    d1["C"].copy_(C0)
+    sg.gemm(d1["A"], d1["B"], d1["C"], levels=0, mode="bf16x3")
+    torch.cuda.synchronize()
+    assert torch.equal(got, d1["C"])
 
 
 @pytest.mark.parametrize("levels", [1, 2])
