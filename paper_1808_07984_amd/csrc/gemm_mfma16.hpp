@@ -1177,30 +1177,33 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
         return;
     }
     if (c_full) {
+        // Per 32x32 block, every output's C reads are issued before any of
+        // its stores (the outputs are distinct blocks), so one read latency
+        // is exposed per block instead of one per output.
 #pragma unroll
         for (int i = 0; i < C::BM; ++i)
 #pragma unroll
             for (int j = 0; j < C::BN; ++j) {
                 const int cj = col0 + wn * C::WN + j * 32 + l32;
                 const int ci0 = row0 + wm * C::WM + i * 32 + 4 * h;
+                float cv[WC][16];
+#pragma unroll
+                for (int o = 0; o < WC; ++o) {
+                    if (crows[o] == 0 || (cfirst[o] && beta == 0.f)) continue;
+                    const float *pc = Cm + coff[o] + (int64_t)ci0 * ldc + cj;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) cv[o][r] = pc[(int64_t)(8 * (r >> 2) + (r & 3)) * ldc];
+                }
 #pragma unroll
                 for (int o = 0; o < WC; ++o) {
                     if (crows[o] == 0) continue;
                     float *pc = Cm + coff[o] + (int64_t)ci0 * ldc + cj;
                     const bool read = !(cfirst[o] && beta == 0.f);
                     const float cb = cfirst[o] ? beta : 1.f;
-                    if (read) {
-                        float cv[16];
 #pragma unroll
-                        for (int r = 0; r < 16; ++r) cv[r] = pc[(int64_t)(8 * (r >> 2) + (r & 3)) * ldc];
-#pragma unroll
-                        for (int r = 0; r < 16; ++r)
-                            pc[(int64_t)(8 * (r >> 2) + (r & 3)) * ldc] = cb * cv[r] + g[o] * acc[i][j][r];
-                    } else {
-#pragma unroll
-                        for (int r = 0; r < 16; ++r)
-                            pc[(int64_t)(8 * (r >> 2) + (r & 3)) * ldc] = g[o] * acc[i][j][r];
-                    }
+                    for (int r = 0; r < 16; ++r)
+                        pc[(int64_t)(8 * (r >> 2) + (r & 3)) * ldc] =
+                            read ? cb * cv[o][r] + g[o] * acc[i][j][r] : g[o] * acc[i][j][r];
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
