@@ -427,6 +427,37 @@ def test_formed0_full_size_bf16x3_equals_plain():
     assert torch.equal(got, d1["C"])
 
 
+@pytest.mark.parametrize("levels,m,n,k", [(0, 4200, 4100, 1001), (1, 5800, 6000, 2566)])
+def test_formed_bf16x3_direct_loads_ragged_integer_exact(levels, m, n, k):
+    """Shapes whose products run the 256 x 256 tiles (direct-to-LDS loads of
+    the pre-split operands) with a ragged last k-tile and edge tiles (both
+    taking the staged loop) and, at one level, the chained launch: integers
+    exact against the oracle, every entry."""
+    prob = make_problem(m, n, k, kind="integers", dtype="bf16x3", c_kind="integers")
+    dev = to_device(prob)
+    assert sg.strassen_profile_start() == 0
+    got = _formed(dev, 1.0, 1.0, "bf16x3", levels=levels)
+    rc, recs = sg.strassen_profile_stop()
+    names = [r.kernel.decode() for r in recs[:rc]]
+    assert any("bf16x3p,256x256" in nm for nm in names), names
+    want = oracle.gemm_f64(prob["A"], prob["B"], prob["C"], 1.0, 1.0)
+    assert np.array_equal(got.cpu().double().numpy(), want)
+
+
+def test_formed2_bf16x3_direct_loads_ragged_sampled():
+    """Two levels at 11600 x 12000 x 2566 (blocks 2900 x 3000 x 644 on 256 x
+    256 tiles: a ragged last k-tile and edge tiles): integer entries sampled
+    in every tile of every C block, exact against the oracle."""
+    m, n, k = 11600, 12000, 2566
+    prob = make_problem(m, n, k, kind="integers", dtype="bf16x3", c_kind="integers")
+    dev = to_device(prob)
+    got = _formed(dev, 1.0, 1.0, "bf16x3", levels=2)
+    rows, cols = stratified_entries(m, n, 2, 3)
+    want = oracle.gemm_entries(prob["A"], prob["B"], prob["C"], rows, cols, 1.0, 1.0)
+    g = got[torch.as_tensor(rows, device="cuda"), torch.as_tensor(cols, device="cuda")].cpu().double().numpy()
+    assert np.array_equal(g, want)
+
+
 @pytest.mark.parametrize("levels", [1, 2])
 @pytest.mark.parametrize("fam", sorted(FAMILIES))
 def test_formed_random_shapes_integer_exact(fam, levels):
