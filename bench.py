@@ -902,8 +902,10 @@ def main():
                                          "padding, A,B,C ~ U[-1,1] seeded", **awkward}
     if compensated is not None:
         result["compensated"] = {"workload": "bf16x3 mode, fp32 A,B ~ N(0,1) seeded, C := A*B, "
-                                             "m=n=k=N; plain (L0), fused one-level, formed one-level "
-                                             "(sums in workspace), fused two-level; median of "
+                                             "m=n=k=N; plain (L0, operands as stored), plain on "
+                                             "pre-split copies (L0_formed), fused and formed one-level "
+                                             "(sums in workspace), fused and formed two-level; "
+                                             "*_vs_L0 against the faster plain (plain_ms); median of "
                                              "interleaved rounds; errors on 256 sampled entries vs "
                                              "fp64 in units of N*max|A|*max|B|*eps", **compensated}
     if precision is not None:
