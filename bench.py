@@ -14,8 +14,9 @@ the library itself on the launch stream.  The CPU oracle is timed on a
 bounded sample of rows of the same product (cpu_baseline); it is used
 nowhere else here: the sampled error checks compare against fp64 dot
 products computed in this script.  Secondary sections: the compensated
-bf16x3 mode at 8192^3 and 16384^3 (plain, fused one-level, formed one-level
-and two-level products timed in interleaved rounds), bf16 / fp16 / bf16x3 at
+bf16x3 mode at 8192^3 and 16384^3 (plain as stored and on pre-split copies,
+fused and formed one- and two-level products timed in interleaved rounds,
+the Strassen speedups taken against the faster plain product), bf16 / fp16 / bf16x3 at
 4096-16384 (N(0,1) and rows/columns scaled over six decades), the fp32
 square and rank-k sweep and the awkward padded shapes, differentiation, and
 small sizes by schedule.
