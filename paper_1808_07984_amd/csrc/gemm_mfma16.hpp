@@ -842,9 +842,8 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
                 if (t + 1 < nfast) issue(t + 1);
                 const unsigned char *ta = reinterpret_cast<const unsigned char *>(&As[t & 1][0][0]);
                 const unsigned char *tb = reinterpret_cast<const unsigned char *>(&Bs[t & 1][0][0]);
-#pragma unroll
-                for (int st = 0; st < NST; ++st) {
-                    u32x4 af[NPLANES][C::BM], bf[NPLANES][C::BN];
+                auto read_frags = [&](int st, u32x4 (&af)[NPLANES][C::BM], u32x4 (&bf)[NPLANES][C::BN])
+                    __attribute__((always_inline)) {
 #pragma unroll
                     for (int i = 0; i < C::BM; ++i) {
                         if constexpr (kDirectPre) {
@@ -864,16 +863,47 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
                             const u32x2 l2 = tr(pb), h2 = tr(pb + 4 * BRB);
                             bf[q][j] = u32x4{l2.x, l2.y, h2.x, h2.y};
                         }
+                };
+                // 16-bit data: the fragments of step st + 1 are read while step
+                // st's MFMAs run, one read per MFMA (+1-3 % bf16 plain, A/B in
+                // one process); the pre-split loop measured 3-8 % slower so,
+                // and reads each step's fragments before its MFMAs
+                if constexpr (kDirect16) {
+                    constexpr int kReads = C::BM + 2 * C::BN;
+                    constexpr int kMfmas = C::BM * C::BN;
+                    u32x4 fa[2][NPLANES][C::BM], fb[2][NPLANES][C::BN];
+                    read_frags(0, fa[0], fb[0]);
 #pragma unroll
-                    for (int i = 0; i < C::BM; ++i)
+                    for (int st = 0; st < NST; ++st) {
+                        if (st + 1 < NST) read_frags(st + 1, fa[(st + 1) & 1], fb[(st + 1) & 1]);
 #pragma unroll
-                        for (int j = 0; j < C::BN; ++j) {
-                            acc[i][j] = mfma(af[0][i], bf[0][j], acc[i][j]);
-                            if constexpr (Ops::kX3) {
+                        for (int i = 0; i < C::BM; ++i)
+#pragma unroll
+                            for (int j = 0; j < C::BN; ++j)
+                                acc[i][j] = mfma(fa[st & 1][0][i], fb[st & 1][0][j], acc[i][j]);
+                        if (st + 1 < NST) {
+#pragma unroll
+                            for (int g = 0; g < kReads; ++g) {
+                                __builtin_amdgcn_sched_group_barrier(0x008, kMfmas / kReads > 0 ? kMfmas / kReads : 1, 0);
+                                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                            }
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                } else {
+#pragma unroll
+                    for (int st = 0; st < NST; ++st) {
+                        u32x4 af[NPLANES][C::BM], bf[NPLANES][C::BN];
+                        read_frags(st, af, bf);
+#pragma unroll
+                        for (int i = 0; i < C::BM; ++i)
+#pragma unroll
+                            for (int j = 0; j < C::BN; ++j) {
+                                acc[i][j] = mfma(af[0][i], bf[0][j], acc[i][j]);
                                 acc[i][j] = mfma(af[0][i], bf[NPLANES - 1][j], acc[i][j]);
                                 acc[i][j] = mfma(af[NPLANES - 1][i], bf[0][j], acc[i][j]);
                             }
-                        }
+                    }
                 }
             }
             kt = nfast;
