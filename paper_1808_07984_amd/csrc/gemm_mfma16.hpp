@@ -833,68 +833,125 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
                     u32x2, __builtin_amdgcn_ds_read_tr16_b64_v4i16(
                                (lds_i16x4 *)(__attribute__((address_space(3))) const unsigned char *)p));
             };
-            issue(0);
-            for (int t = 0; t < nfast; ++t) {
+            // fragments of MFMA step st of the tile in LDS buffer b
+            auto read_frags = [&](int b, int st, u32x4 (&af)[NPLANES][C::BM], u32x4 (&bf)[NPLANES][C::BN])
+                __attribute__((always_inline)) {
+                const unsigned char *ta = reinterpret_cast<const unsigned char *>(&As[b][0][0]);
+                const unsigned char *tb = reinterpret_cast<const unsigned char *>(&Bs[b][0][0]);
+#pragma unroll
+                for (int i = 0; i < C::BM; ++i) {
+                    if constexpr (kDirectPre) {
+                        const u32x4 u0 = *reinterpret_cast<const u32x4 *>(ta + a_rd[st][0] + 4096 * i);
+                        const u32x4 u1 = *reinterpret_cast<const u32x4 *>(ta + a_rd[st][1] + 4096 * i);
+                        af[0][i] = u32x4{u0[0], u0[1], u1[0], u1[1]};
+                        af[NPLANES - 1][i] = u32x4{u0[2], u0[3], u1[2], u1[3]};
+                    } else {
+                        af[0][i] = *reinterpret_cast<const u32x4 *>(ta + a_rd[st][0] + 4096 * i);
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < C::BN; ++j)
+#pragma unroll
+                    for (int q = 0; q < NPLANES; ++q) {  // plane q: the unit's half at byte 8 q
+                        const unsigned char *pb = tb + b_rd[j] + 16 * st * BRB + 8 * q;
+                        const u32x2 l2 = tr(pb), h2 = tr(pb + 4 * BRB);
+                        bf[q][j] = u32x4{l2.x, l2.y, h2.x, h2.y};
+                    }
+            };
+            // every wave's loads into LDS have landed and every wave is past
+            // the reads of the buffer the next loads overwrite
+            auto tile_barrier = [&]() __attribute__((always_inline)) {
                 wait_vmcnt<0>();
                 __builtin_amdgcn_sched_barrier(0);
                 asm volatile("s_barrier" ::: "memory");
                 __builtin_amdgcn_sched_barrier(0);
-                if (t + 1 < nfast) issue(t + 1);
-                const unsigned char *ta = reinterpret_cast<const unsigned char *>(&As[t & 1][0][0]);
-                const unsigned char *tb = reinterpret_cast<const unsigned char *>(&Bs[t & 1][0][0]);
-                auto read_frags = [&](int st, u32x4 (&af)[NPLANES][C::BM], u32x4 (&bf)[NPLANES][C::BN])
-                    __attribute__((always_inline)) {
+            };
+            issue(0);
+            if constexpr (kDirect16) {
+                // 16-bit data: the fragments of step st + 1 are read while
+                // step st's MFMAs run, one read per MFMA (+1-3 % bf16 plain,
+                // A/B in one process), and the tile boundary sits inside the
+                // last step: its fragments are already in registers, so after
+                // its first row of MFMAs the wave waits for its own LDS reads
+                // and loads, meets the others at the barrier, issues the loads
+                // of tile t + 2 into the buffer just read, and reads step 0 of
+                // tile t + 1 while the rest of the step's MFMAs run.  The
+                // barrier, the load issue and the first reads' latency no
+                // longer leave the matrix cores idle between tiles.
+                constexpr int kReads = C::BM + 2 * C::BN;
+                constexpr int kMfmas = C::BM * C::BN;
+                constexpr int kLast = (NST - 1) & 1;
+                static_assert(NST % 2 == 0 && C::BM >= 2, "step 0 of a tile reads into fragment set 0");
+                u32x4 fa[2][NPLANES][C::BM], fb[2][NPLANES][C::BN];
+                tile_barrier();
+                if (1 < nfast) issue(1);
+                read_frags(0, 0, fa[0], fb[0]);
+                auto tile = [&](int t, auto more) __attribute__((always_inline)) {
+                    const int b = t & 1;
 #pragma unroll
-                    for (int i = 0; i < C::BM; ++i) {
-                        if constexpr (kDirectPre) {
-                            const u32x4 u0 = *reinterpret_cast<const u32x4 *>(ta + a_rd[st][0] + 4096 * i);
-                            const u32x4 u1 = *reinterpret_cast<const u32x4 *>(ta + a_rd[st][1] + 4096 * i);
-                            af[0][i] = u32x4{u0[0], u0[1], u1[0], u1[1]};
-                            af[NPLANES - 1][i] = u32x4{u0[2], u0[3], u1[2], u1[3]};
-                        } else {
-                            af[0][i] = *reinterpret_cast<const u32x4 *>(ta + a_rd[st][0] + 4096 * i);
-                        }
-                    }
-#pragma unroll
-                    for (int j = 0; j < C::BN; ++j)
-#pragma unroll
-                        for (int q = 0; q < NPLANES; ++q) {  // plane q: the unit's half at byte 8 q
-                            const unsigned char *pb = tb + b_rd[j] + 16 * st * BRB + 8 * q;
-                            const u32x2 l2 = tr(pb), h2 = tr(pb + 4 * BRB);
-                            bf[q][j] = u32x4{l2.x, l2.y, h2.x, h2.y};
-                        }
-                };
-                // 16-bit data: the fragments of step st + 1 are read while step
-                // st's MFMAs run, one read per MFMA (+1-3 % bf16 plain, A/B in
-                // one process); the pre-split loop measured 3-8 % slower so,
-                // and reads each step's fragments before its MFMAs
-                if constexpr (kDirect16) {
-                    constexpr int kReads = C::BM + 2 * C::BN;
-                    constexpr int kMfmas = C::BM * C::BN;
-                    u32x4 fa[2][NPLANES][C::BM], fb[2][NPLANES][C::BN];
-                    read_frags(0, fa[0], fb[0]);
-#pragma unroll
-                    for (int st = 0; st < NST; ++st) {
-                        if (st + 1 < NST) read_frags(st + 1, fa[(st + 1) & 1], fb[(st + 1) & 1]);
+                    for (int st = 0; st + 1 < NST; ++st) {
+                        read_frags(b, st + 1, fa[(st + 1) & 1], fb[(st + 1) & 1]);
 #pragma unroll
                         for (int i = 0; i < C::BM; ++i)
 #pragma unroll
                             for (int j = 0; j < C::BN; ++j)
                                 acc[i][j] = mfma(fa[st & 1][0][i], fb[st & 1][0][j], acc[i][j]);
-                        if (st + 1 < NST) {
 #pragma unroll
-                            for (int g = 0; g < kReads; ++g) {
-                                __builtin_amdgcn_sched_group_barrier(0x008, kMfmas / kReads > 0 ? kMfmas / kReads : 1, 0);
-                                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-                            }
+                        for (int g = 0; g < kReads; ++g) {
+                            __builtin_amdgcn_sched_group_barrier(0x008, kMfmas / kReads > 0 ? kMfmas / kReads : 1, 0);
+                            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
                         }
                         __builtin_amdgcn_sched_barrier(0);
                     }
-                } else {
+                    if constexpr (decltype(more)::value) {
+#pragma unroll
+                        for (int j = 0; j < C::BN; ++j)
+                            acc[0][j] = mfma(fa[kLast][0][0], fb[kLast][0][j], acc[0][j]);
+                        __builtin_amdgcn_sched_barrier(0);
+                        // vmcnt(0) and lgkmcnt(0): tile t + 1 has landed and
+                        // this wave's reads of tile t have returned
+                        __builtin_amdgcn_s_waitcnt((7 << 4));
+                        __builtin_amdgcn_sched_barrier(0);
+                        asm volatile("s_barrier" ::: "memory");
+                        __builtin_amdgcn_sched_barrier(0);
+                        if (t + 2 < nfast) issue(t + 2);
+                        read_frags(b ^ 1, 0, fa[0], fb[0]);
+#pragma unroll
+                        for (int i = 1; i < C::BM; ++i)
+#pragma unroll
+                            for (int j = 0; j < C::BN; ++j)
+                                acc[i][j] = mfma(fa[kLast][0][i], fb[kLast][0][j], acc[i][j]);
+                        constexpr int kRest = kMfmas - C::BN;
+                        __builtin_amdgcn_sched_group_barrier(0x100, kReads > kRest ? kReads - kRest : 0, 0);
+#pragma unroll
+                        for (int g = 0; g < (kReads < kRest ? kReads : kRest); ++g) {
+                            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < C::BM; ++i)
+#pragma unroll
+                            for (int j = 0; j < C::BN; ++j)
+                                acc[i][j] = mfma(fa[kLast][0][i], fb[kLast][0][j], acc[i][j]);
+                    }
+                };
+                int t = 0;
+                for (; t + 1 < nfast; ++t) tile(t, std::true_type{});
+                tile(t, std::false_type{});
+            } else {
+                // pre-split data: each step's fragments are read before its
+                // MFMAs (reading the next step's during them, with fragment
+                // pairs taking twice the reads and registers, measured 3-8 %
+                // slower)
+                for (int t = 0; t < nfast; ++t) {
+                    tile_barrier();
+                    if (t + 1 < nfast) issue(t + 1);
 #pragma unroll
                     for (int st = 0; st < NST; ++st) {
                         u32x4 af[NPLANES][C::BM], bf[NPLANES][C::BN];
-                        read_frags(st, af, bf);
+                        read_frags(t & 1, st, af, bf);
 #pragma unroll
                         for (int i = 0; i < C::BM; ++i)
 #pragma unroll
