@@ -162,8 +162,14 @@ def tile_mode(request):
 @pytest.mark.parametrize("kind", sorted(MODES))
 @pytest.mark.parametrize("levels", [0, 1, 2])
 @pytest.mark.parametrize("m,n,k", [(3, 5, 7), (65, 67, 63), (301, 257, 190), (520, 700, 333),
-                                   (1100, 1060, 600)])
+                                   (1100, 1060, 600), (512, 512, 128), (600, 300, 100), (512, 256, 64)])
 def test_lowp_integer_exact_each_tile(tile_mode, kind, levels, m, n, k):
+    """Integers exact against the oracle on both tile sizes.  On 256 x 256
+    tiles the interior tiles of the bf16 and fp16 single-term products load
+    their whole 64-deep k-tiles straight into LDS (at level 0 here): one
+    such k-tile without a ragged end (512 x 256 x 64) and with one (600 x
+    300 x 100), two without (512^2 x 128) and two or more with one (301 x
+    257 x 190 and the larger shapes)."""
     dtype, mode = MODES[kind]
     prob = make_problem(m, n, k, kind="integers", dtype=dtype, c_kind="integers")
     dev = _run(prob, levels, 1.0, 1.0, mode)
