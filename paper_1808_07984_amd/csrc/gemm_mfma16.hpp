@@ -204,6 +204,10 @@ __device__ __forceinline__ void wait_vmcnt() {
     __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
+// Waits until none of this wave's vector-memory loads and LDS reads is in
+// flight (expcnt is left alone).
+__device__ __forceinline__ void wait_vmcnt_lgkmcnt0() { __builtin_amdgcn_s_waitcnt(7 << 4); }
+
 typedef short i16x4 __attribute__((ext_vector_type(4)));
 
 // PRE: a pre-split operand (whole 16-byte units only: a unit that crosses the
@@ -909,9 +913,9 @@ void strassen_m16_kernel(const LaunchArgs args, const int vec) {
                         for (int j = 0; j < C::BN; ++j)
                             acc[0][j] = mfma(fa[kLast][0][0], fb[kLast][0][j], acc[0][j]);
                         __builtin_amdgcn_sched_barrier(0);
-                        // vmcnt(0) and lgkmcnt(0): tile t + 1 has landed and
-                        // this wave's reads of tile t have returned
-                        __builtin_amdgcn_s_waitcnt((7 << 4));
+                        // tile t + 1 has landed and this wave's reads of
+                        // tile t have returned
+                        wait_vmcnt_lgkmcnt0();
                         __builtin_amdgcn_sched_barrier(0);
                         asm volatile("s_barrier" ::: "memory");
                         __builtin_amdgcn_sched_barrier(0);
